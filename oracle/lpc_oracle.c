@@ -1,0 +1,242 @@
+/*
+ * Plain FP64 CPU oracle for the LPC3D lattice sweep. TEST INFRASTRUCTURE ONLY: it is
+ * called by the tests, by the entry point's smoke check and by the benchmark's CPU
+ * baseline, never by the library. It shares no code with the GPU path.
+ *
+ * What one time step computes (LPC3D paper, section 2, "Description of the model"
+ * and "NMR spectra"; section 3.1, Eqs. (10)-(13)):
+ *
+ *  - Hop probability from site i to nearest neighbour j (simple cubic lattice, six
+ *    neighbours): p(i->j) = p0 * P(i->j), where P is the Metropolis acceptance of
+ *    Eq. (1): exp(-(F_j - F_i)) if F_j > F_i, else 1 (F in units of kT). p0 is the
+ *    per-neighbour attempt probability (alpha / 6 in the notation of Eq. (7)).
+ *  - A particle that does not hop stays (Fig. 1 caption): stay(i) = 1 - sum_j p(i->j),
+ *    where attempts across a closed face have no target and count as staying.
+ *  - Populations (densities, not particles; end of section 2.1):
+ *        rho'_i = stay(i) rho_i + sum_j p(j->i) rho_j.
+ *  - Magnetisation, Eq. (13) in 3-D with the stay term: gather first, then rotate by
+ *    the destination's phase per step theta_i = 2 pi delta_i 1e-6 nu0 dt (Eq. (11)):
+ *        m'_i = exp(i theta_i) [ stay(i) m_i + sum_j p(j->i) m_j ].
+ *  - Displacement moments (moment propagation, section 2.2) per axis a, with d_a the
+ *    unwrapped a-component of the hop vector j -> i:
+ *        M1'_i = stay(i) M1_i + sum_j p(j->i) (M1_j + d_a rho_j)
+ *        M2'_i = stay(i) M2_i + sum_j p(j->i) (M2_j + 2 d_a M1_j + d_a^2 rho_j).
+ *  - Records after every step (and before the first), Eqs. (11)-(12): per region r the
+ *    sums of m (real, imaginary) and rho, and over all sites the sums of M1_a, M2_a.
+ *    Record layout, K = 3R + 6 doubles: [Re G_r, Im G_r] for r < R, then U_r for r < R,
+ *    then S1_x, S1_y, S1_z, S2_x, S2_y, S2_z.
+ *
+ * Boundaries: a periodic axis wraps the neighbour index (the hop vector stays +-1); a
+ * closed axis has no neighbour beyond its faces.
+ *
+ * Plain loops over z, y, x; OpenMP splits z-planes only. Record sums are taken per
+ * z-plane in index order and then over planes in order, so results do not depend on
+ * the thread count.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORACLE_PERIODIC 0
+#define ORACLE_CLOSED 1
+
+static const int HOP[6][3] = {
+    {+1, 0, 0}, {-1, 0, 0}, {0, +1, 0}, {0, -1, 0}, {0, 0, +1}, {0, 0, -1}};
+
+/* Metropolis acceptance of a move from free energy Fi to Fj (kT units), Eq. (1). */
+static double acceptance(double Fi, double Fj)
+{
+    if (Fj > Fi)
+        return exp(-(Fj - Fi));
+    return 1.0;
+}
+
+typedef struct {
+    int64_t n[3];
+    int bc[3];
+} geometry;
+
+/* Index of the neighbour of (x, y, z) one hop along direction d, or -1 across a closed face. */
+static int64_t neighbour(const geometry *g, int64_t x, int64_t y, int64_t z, int d)
+{
+    int64_t c[3] = {x + HOP[d][0], y + HOP[d][1], z + HOP[d][2]};
+    for (int a = 0; a < 3; ++a) {
+        if (c[a] < 0 || c[a] >= g->n[a]) {
+            if (g->bc[a] == ORACLE_CLOSED)
+                return -1;
+            c[a] = (c[a] + g->n[a]) % g->n[a];
+        }
+    }
+    return c[0] + g->n[0] * (c[1] + g->n[1] * c[2]);
+}
+
+typedef struct {
+    double *rho, *re, *im, *M1, *M2; /* M1, M2: 3 blocks of n (axis-major) or NULL */
+} state;
+
+static void one_step(const geometry *g, double p0, const double *F, const double *cos_t,
+                     const double *sin_t, const state *s, state *o)
+{
+    const int64_t nx = g->n[0], ny = g->n[1], nz = g->n[2];
+    const int64_t n = nx * ny * nz;
+    const int moments = s->M1 != NULL;
+#pragma omp parallel for schedule(static)
+    for (int64_t z = 0; z < nz; ++z) {
+        for (int64_t y = 0; y < ny; ++y) {
+            for (int64_t x = 0; x < nx; ++x) {
+                const int64_t i = x + nx * (y + ny * z);
+                double out = 0.0;
+                double in_rho = 0.0, in_re = 0.0, in_im = 0.0;
+                double in1[3] = {0.0, 0.0, 0.0}, in2[3] = {0.0, 0.0, 0.0};
+                for (int d = 0; d < 6; ++d) {
+                    const int64_t j = neighbour(g, x, y, z, d);
+                    if (j < 0)
+                        continue; /* attempt across a closed face: the particle stays */
+                    const double p_out = p0 * acceptance(F[i], F[j]); /* i -> j */
+                    const double p_in = p0 * acceptance(F[j], F[i]);  /* j -> i */
+                    out += p_out;
+                    in_rho += p_in * s->rho[j];
+                    in_re += p_in * s->re[j];
+                    in_im += p_in * s->im[j];
+                    if (moments) {
+                        for (int a = 0; a < 3; ++a) {
+                            const double da = -HOP[d][a]; /* the move j -> i goes against d */
+                            const double m1 = s->M1[a * n + j], m2 = s->M2[a * n + j];
+                            in1[a] += p_in * (m1 + da * s->rho[j]);
+                            in2[a] += p_in * (m2 + 2.0 * da * m1 + da * da * s->rho[j]);
+                        }
+                    }
+                }
+                const double stay = 1.0 - out;
+                o->rho[i] = stay * s->rho[i] + in_rho;
+                const double gre = stay * s->re[i] + in_re;
+                const double gim = stay * s->im[i] + in_im;
+                o->re[i] = gre * cos_t[i] - gim * sin_t[i];
+                o->im[i] = gre * sin_t[i] + gim * cos_t[i];
+                if (moments) {
+                    for (int a = 0; a < 3; ++a) {
+                        o->M1[a * n + i] = stay * s->M1[a * n + i] + in1[a];
+                        o->M2[a * n + i] = stay * s->M2[a * n + i] + in2[a];
+                    }
+                }
+            }
+        }
+    }
+}
+
+static void record(const geometry *g, const uint8_t *region, int R, const state *s,
+                   double *plane_buf, double *rec)
+{
+    const int64_t nx = g->n[0], ny = g->n[1], nz = g->n[2];
+    const int64_t n = nx * ny * nz, plane = nx * ny;
+    const int K = 3 * R + 6;
+#pragma omp parallel for schedule(static)
+    for (int64_t z = 0; z < nz; ++z) {
+        double *acc = plane_buf + z * K;
+        for (int k = 0; k < K; ++k)
+            acc[k] = 0.0;
+        for (int64_t q = 0; q < plane; ++q) {
+            const int64_t i = z * plane + q;
+            const int r = region[i];
+            acc[2 * r] += s->re[i];
+            acc[2 * r + 1] += s->im[i];
+            acc[2 * R + r] += s->rho[i];
+            if (s->M1 != NULL) {
+                for (int a = 0; a < 3; ++a) {
+                    acc[3 * R + a] += s->M1[a * n + i];
+                    acc[3 * R + 3 + a] += s->M2[a * n + i];
+                }
+            }
+        }
+    }
+    for (int k = 0; k < K; ++k)
+        rec[k] = 0.0;
+    for (int64_t z = 0; z < nz; ++z)
+        for (int k = 0; k < K; ++k)
+            rec[k] += plane_buf[z * K + k];
+}
+
+int lpc_oracle_record_width(int n_regions) { return 3 * n_regions + 6; }
+
+int lpc_oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/*
+ * Runs n_steps steps from the state held in rho, re, im (and M1, M2 when non-NULL; each
+ * 3*n doubles, axis-major), overwriting it with the final state. records receives
+ * (n_steps + 1) * (3 R + 6) doubles: the record of the initial state, then one per step.
+ * Returns 0 on success, 1 on a bad argument, 2 when memory runs out.
+ */
+int lpc_oracle_run(int64_t nx, int64_t ny, int64_t nz, const int32_t *bc, double p0,
+                   double dt_s, double larmor_hz, const double *F, const double *delta_ppm,
+                   const uint8_t *region, int32_t n_regions, double *rho, double *re,
+                   double *im, double *M1, double *M2, int64_t n_steps, double *records)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || n_regions < 1 || n_steps < 0 || !F || !delta_ppm ||
+        !region || !rho || !re || !im || !records || ((M1 == NULL) != (M2 == NULL)))
+        return 1;
+    geometry g = {{nx, ny, nz}, {bc[0], bc[1], bc[2]}};
+    const int64_t n = nx * ny * nz;
+    const int K = 3 * n_regions + 6;
+    const int moments = M1 != NULL;
+    double *cos_t = malloc(sizeof(double) * n), *sin_t = malloc(sizeof(double) * n);
+    double *plane_buf = malloc(sizeof(double) * nz * K);
+    state a = {rho, re, im, M1, M2};
+    state b = {malloc(sizeof(double) * n), malloc(sizeof(double) * n),
+               malloc(sizeof(double) * n), moments ? malloc(sizeof(double) * 3 * n) : NULL,
+               moments ? malloc(sizeof(double) * 3 * n) : NULL};
+    int rc = 0;
+    if (!cos_t || !sin_t || !plane_buf || !b.rho || !b.re || !b.im ||
+        (moments && (!b.M1 || !b.M2))) {
+        rc = 2;
+        goto done;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        if (region[i] >= n_regions) {
+            rc = 1;
+            goto done;
+        }
+        /* phase accumulated in one step at the site's Larmor offset, Eq. (11) */
+        const double theta = 2.0 * M_PI * delta_ppm[i] * 1e-6 * larmor_hz * dt_s;
+        cos_t[i] = cos(theta);
+        sin_t[i] = sin(theta);
+    }
+    record(&g, region, n_regions, &a, plane_buf, records);
+    state *cur = &a, *nxt = &b;
+    for (int64_t t = 1; t <= n_steps; ++t) {
+        one_step(&g, p0, F, cos_t, sin_t, cur, nxt);
+        record(&g, region, n_regions, nxt, plane_buf, records + t * K);
+        state *tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+    }
+    if (cur != &a) {
+        memcpy(a.rho, cur->rho, sizeof(double) * n);
+        memcpy(a.re, cur->re, sizeof(double) * n);
+        memcpy(a.im, cur->im, sizeof(double) * n);
+        if (moments) {
+            memcpy(a.M1, cur->M1, sizeof(double) * 3 * n);
+            memcpy(a.M2, cur->M2, sizeof(double) * 3 * n);
+        }
+    }
+done:
+    free(cos_t);
+    free(sin_t);
+    free(plane_buf);
+    free(b.rho);
+    free(b.re);
+    free(b.im);
+    free(b.M1);
+    free(b.M2);
+    return rc;
+}
