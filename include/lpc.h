@@ -1,0 +1,159 @@
+/*
+ * lpc.h -- C ABI of liblpc, the MI355X lattice sweep of the LPC3D mesoscopic model.
+ *
+ * The model (LPC3D paper, section 2): densities of non-interacting species on a simple
+ * cubic lattice hop between nearest neighbours with Metropolis probabilities set by
+ * site free energies (Eq. (1)); their Boltzmann distribution (Eq. (2)) is stationary.
+ * Moment propagation (section 2.2) carries displacement moments for diffusion
+ * coefficients (Eqs. (4)-(7)); the complex magnetisation of each site is gathered from
+ * its neighbours and rotated by the site's chemical-shift phase every step (Eqs. (8),
+ * (10)-(13)), and its sum over sites is the free-induction decay (FID) whose Fourier
+ * transform is the NMR spectrum (Eq. (9)).
+ *
+ * One step, per site i with neighbours j (attempt probability p0 per neighbour):
+ *   p(i->j)  = p0 * min(1, exp(-(F_j - F_i)))           F in units of kT
+ *   stay(i)  = 1 - sum_j p(i->j)                         closed faces: no neighbour
+ *   rho'_i   = stay(i) rho_i + sum_j p(j->i) rho_j
+ *   m'_i     = exp(i theta_i) [stay(i) m_i + sum_j p(j->i) m_j],
+ *              theta_i = 2 pi delta_i[ppm] 1e-6 larmor_hz dt_s
+ *   M1'_a,i  = stay(i) M1_a,i + sum_j p(j->i) (M1_a,j + d_a rho_j)
+ *   M2'_a,i  = stay(i) M2_a,i + sum_j p(j->i) (M2_a,j + 2 d_a M1_a,j + d_a^2 rho_j)
+ * with d_a the unwrapped a-component of the hop j -> i. After every step, and once for
+ * the initial state, the library records in FP64, per region r, Re/Im of sum m and
+ * sum rho, and over all sites sum M1_a and sum M2_a.
+ *
+ * Conventions
+ *  - Every call returns an lpc_status; on error the out-parameters are left untouched
+ *    and lpc_last_error() returns a message (thread-local). Nothing aborts and no C++
+ *    exception crosses this boundary.
+ *  - Device memory: the caller owns one device buffer (the arena) of at least
+ *    lpc_query_footprint() bytes, aligned to 256 bytes, for the lifetime of the lattice.
+ *    The library places all of its device data in it and never allocates or frees device
+ *    memory itself.
+ *  - Host arrays passed in are copied before the call returns; no pointer is kept.
+ *  - Host site arrays hold nx*ny*nz values with x fastest: index x + nx*(y + ny*z).
+ *  - Streams: work is queued on the stream given at creation (a hipStream_t passed as
+ *    void*, NULL = the null stream). lpc_run returns once the work is queued; device
+ *    errors surface at the next lpc_synchronize or read. Reads synchronize the stream.
+ *  - A handle is not thread-safe: one thread at a time may use it.
+ */
+#ifndef LPC_H
+#define LPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lpc_status {
+    LPC_OK = 0,
+    LPC_ERR_ARG = 1,          /* bad argument: NULL, size mismatch, out of range */
+    LPC_ERR_OOM = 2,          /* arena or host buffer too small */
+    LPC_ERR_DEVICE = 3,       /* a HIP call failed */
+    LPC_ERR_STATE = 4,        /* call out of order, or record capacity exceeded */
+    LPC_ERR_NONFINITE = 5,    /* NaN/Inf in an input, or in the recorded FID */
+    LPC_ERR_CONSERVATION = 6  /* total population drifted beyond conservation_tol */
+} lpc_status;
+
+enum { LPC_BC_PERIODIC = 0, LPC_BC_CLOSED = 1 };
+
+/* FP64: every field and state array in double. MIXED: populations in double, free
+ * energy, phase and the magnetisation / moment arrays stored in float; all arithmetic
+ * of the update and every record sum in double. */
+enum { LPC_PREC_FP64 = 0, LPC_PREC_MIXED = 1 };
+
+/* Track set. Populations are always propagated. */
+enum { LPC_TRACK_FID = 1u, LPC_TRACK_MSD = 2u };
+
+enum { LPC_INIT_UNIFORM = 0, LPC_INIT_BOLTZMANN = 1, LPC_INIT_USER = 2 };
+
+#define LPC_MAX_REGIONS 8
+
+typedef struct lpc_config {
+    int32_t n[3];             /* nx, ny, nz >= 1 */
+    int32_t bc[3];            /* LPC_BC_PERIODIC or LPC_BC_CLOSED, per axis */
+    int32_t precision;        /* LPC_PREC_FP64 or LPC_PREC_MIXED */
+    uint32_t track;           /* LPC_TRACK_FID | LPC_TRACK_MSD (0 = populations only) */
+    int32_t n_regions;        /* 1..LPC_MAX_REGIONS */
+    int32_t reserved;         /* must be 0 */
+    double p_hop;             /* attempt probability per neighbour, 0 <= 6 p_hop <= 1 (1/7) */
+    double dt_s;              /* time step in seconds (5e-6) */
+    double larmor_hz;         /* spectrometer Larmor frequency (400e6) */
+    double spacing_m;         /* lattice spacing a in metres (0.5e-9) */
+    int64_t max_records;      /* record rows kept: the initial state + steps, >= 1 */
+    double conservation_tol;  /* relative mass drift that reads report; 0 disables */
+} lpc_config;
+
+typedef struct lpc_lattice lpc_lattice;
+typedef struct lpc_batch lpc_batch;
+
+/* Fills the defaults above for an n^3 periodic FP64 lattice with full tracking. */
+lpc_status lpc_config_default(lpc_config *cfg, int32_t n);
+
+/* Device bytes the lattice needs for cfg (fields, two state buffers, per-step
+ * partial sums, records and a staging area). */
+lpc_status lpc_query_footprint(const lpc_config *cfg, size_t *bytes);
+
+/* Creates a lattice in the caller's arena (device pointer, >= footprint bytes, 256-byte
+ * aligned). Fields start at F = 0, delta = 0, region 0; the state is uninitialised until
+ * lpc_init_state. stream: hipStream_t as void*. */
+lpc_status lpc_create(const lpc_config *cfg, void *arena, size_t arena_bytes, void *stream,
+                      lpc_lattice **out);
+lpc_status lpc_destroy(lpc_lattice *lat);
+
+/* Site free energies in kT (Eq. (1)); n must be nx*ny*nz; NaN/Inf -> LPC_ERR_NONFINITE. */
+lpc_status lpc_set_free_energy(lpc_lattice *lat, const double *F_kT, int64_t n);
+/* Site chemical shifts in ppm (Eq. (11) phase per step); NaN/Inf -> LPC_ERR_NONFINITE. */
+lpc_status lpc_set_shift(lpc_lattice *lat, const double *delta_ppm, int64_t n);
+/* Region id per site, each < n_regions, else LPC_ERR_ARG. */
+lpc_status lpc_set_regions(lpc_lattice *lat, const uint8_t *region, int64_t n);
+
+/* Initial state: UNIFORM rho = 1; BOLTZMANN rho_i = N exp(-F_i) / sum_j exp(-F_j)
+ * (Eq. (2), mean density 1); USER rho from the host array (finite, n values). In every
+ * mode m = rho (real), M1 = M2 = 0, the step counter is reset and record row 0 is
+ * written. rho may be NULL unless mode is USER. */
+lpc_status lpc_init_state(lpc_lattice *lat, int32_t mode, const double *rho, int64_t n);
+
+/* Queues n_steps steps. LPC_ERR_STATE if not initialised or if steps_done + n_steps
+ * would exceed max_records - 1. */
+lpc_status lpc_run(lpc_lattice *lat, int64_t n_steps);
+lpc_status lpc_synchronize(lpc_lattice *lat);
+lpc_status lpc_steps_done(const lpc_lattice *lat, int64_t *n);
+
+/* Record width K = 3 R + 6 and raw records: rows of [Re G_r, Im G_r] (r < R),
+ * U_r (r < R), S1_x, S1_y, S1_z, S2_x, S2_y, S2_z; row t is after t steps. */
+lpc_status lpc_record_width(const lpc_lattice *lat, int32_t *K);
+lpc_status lpc_read_records(lpc_lattice *lat, double *records, int64_t cap_rows, int64_t *rows);
+
+/* Final-state arrays (n values each, double). */
+lpc_status lpc_read_population(lpc_lattice *lat, double *rho, int64_t n);
+lpc_status lpc_read_magnetization(lpc_lattice *lat, double *re, double *im, int64_t n);
+
+/* Derived record series (steps_done + 1 rows). These check the run first: a non-finite
+ * FID gives LPC_ERR_NONFINITE and a relative mass drift above conservation_tol gives
+ * LPC_ERR_CONSERVATION. region = -1 sums all regions. msd/drift: S2/mass, S1/mass
+ * per axis, 3 values per row. uptake: R values per row. */
+lpc_status lpc_read_fid(lpc_lattice *lat, int32_t region, double *re, double *im, int64_t cap,
+                        int64_t *len);
+lpc_status lpc_read_moments(lpc_lattice *lat, double *mass, double *msd_xyz, double *drift_xyz,
+                            int64_t cap, int64_t *len);
+lpc_status lpc_read_uptake(lpc_lattice *lat, double *per_step_per_region, int64_t cap,
+                           int64_t *len);
+lpc_status lpc_check(lpc_lattice *lat);
+
+/* Checkpoint: the state arrays, step counter and records, into / from host memory.
+ * With buf == NULL, save reports the size needed in *len. Load requires a lattice of
+ * the same configuration; fields are not part of the checkpoint. */
+lpc_status lpc_save_state(lpc_lattice *lat, void *buf, size_t cap, size_t *len);
+lpc_status lpc_load_state(lpc_lattice *lat, const void *buf, size_t len);
+
+const char *lpc_last_error(void);
+const char *lpc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LPC_H */

@@ -1,0 +1,837 @@
+// C-ABI of liblpc: lattice lifetime, arena layout, field set-up, run loop, reads and
+// checkpoints. The operation itself is defined in include/lpc.h and the kernels live in
+// sweep.hip; this file only validates arguments, places buffers in the caller's arena and
+// queues work on the caller's stream.
+#include "lpc.h"
+#include "lpc_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_error;
+
+lpc_status fail(lpc_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return st;
+}
+
+lpc_status ok()
+{
+    return LPC_OK;
+}
+
+#define LPC_HIP(call)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(LPC_ERR_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_));      \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int64_t kStagingMax = int64_t(1) << 22;   // doubles per host<->device chunk
+constexpr int64_t kPartialBudget = int64_t(32) << 20; // bytes of per-step partials per chunk
+constexpr int64_t kChunkMax = 256;                    // steps finalised together
+constexpr int kScalars = 64;
+
+size_t align_up(size_t v)
+{
+    return (v + kAlign - 1) / kAlign * kAlign;
+}
+
+struct Layout {
+    int64_t n = 0;
+    int K = 0;
+    size_t storage = 8;
+    lpc::SweepPlan plan{};
+    int64_t chunk = 1;
+    int64_t staging = 0;
+    size_t off_F = 0, off_theta = 0, off_region = 0, off_partials = 0, off_records = 0,
+           off_staging = 0, off_scalars = 0;
+    size_t off_rho[2] = {0, 0}, off_re[2] = {0, 0}, off_im[2] = {0, 0};
+    size_t off_m1[2][3] = {}, off_m2[2][3] = {};
+    size_t total = 0;
+};
+
+bool fid_of(const lpc_config &c)
+{
+    return (c.track & LPC_TRACK_FID) != 0;
+}
+bool msd_of(const lpc_config &c)
+{
+    return (c.track & LPC_TRACK_MSD) != 0;
+}
+
+lpc_status validate_config(const lpc_config *c)
+{
+    if (!c)
+        return fail(LPC_ERR_ARG, "config is NULL");
+    for (int a = 0; a < 3; ++a) {
+        if (c->n[a] < 1)
+            return fail(LPC_ERR_ARG, "n[%d] = %d must be >= 1", a, c->n[a]);
+        if (c->bc[a] != LPC_BC_PERIODIC && c->bc[a] != LPC_BC_CLOSED)
+            return fail(LPC_ERR_ARG, "bc[%d] = %d is not PERIODIC or CLOSED", a, c->bc[a]);
+    }
+    if (int64_t(c->n[0]) * c->n[1] > (int64_t(1) << 31))
+        return fail(LPC_ERR_ARG, "nx * ny must not exceed 2^31");
+    if (c->precision != LPC_PREC_FP64 && c->precision != LPC_PREC_MIXED)
+        return fail(LPC_ERR_ARG, "precision %d unknown", c->precision);
+    if (c->track & ~uint32_t(LPC_TRACK_FID | LPC_TRACK_MSD))
+        return fail(LPC_ERR_ARG, "track bits 0x%x unknown", c->track);
+    if (c->n_regions < 1 || c->n_regions > LPC_MAX_REGIONS)
+        return fail(LPC_ERR_ARG, "n_regions = %d outside 1..%d", c->n_regions, LPC_MAX_REGIONS);
+    if (c->reserved != 0)
+        return fail(LPC_ERR_ARG, "reserved field must be 0");
+    if (!std::isfinite(c->p_hop) || c->p_hop < 0.0 || 6.0 * c->p_hop > 1.0)
+        return fail(LPC_ERR_ARG, "p_hop = %g must satisfy 0 <= 6 p_hop <= 1", c->p_hop);
+    if (!std::isfinite(c->dt_s) || !std::isfinite(c->larmor_hz) || !std::isfinite(c->spacing_m) ||
+        c->dt_s <= 0.0 || c->spacing_m <= 0.0)
+        return fail(LPC_ERR_ARG, "dt_s and spacing_m must be positive, larmor_hz finite");
+    if (c->max_records < 1)
+        return fail(LPC_ERR_ARG, "max_records must be >= 1");
+    if (!std::isfinite(c->conservation_tol) || c->conservation_tol < 0.0)
+        return fail(LPC_ERR_ARG, "conservation_tol must be >= 0");
+    return LPC_OK;
+}
+
+Layout plan_layout(const lpc_config &c)
+{
+    Layout L;
+    L.n = int64_t(c.n[0]) * c.n[1] * c.n[2];
+    L.K = 3 * c.n_regions + 6;
+    L.storage = c.precision == LPC_PREC_FP64 ? 8 : 4;
+    lpc::Geometry g{c.n[0], c.n[1], c.n[2], {c.bc[0], c.bc[1], c.bc[2]}};
+    L.plan = lpc::make_plan(g, 0);
+    const int64_t per_step = int64_t(L.K) * L.plan.nblocks * 8;
+    L.chunk = kPartialBudget / per_step;
+    if (L.chunk > kChunkMax)
+        L.chunk = kChunkMax;
+    if (L.chunk < 1)
+        L.chunk = 1;
+    L.staging = L.n < kStagingMax ? L.n : kStagingMax;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    const size_t ns = size_t(L.n) * L.storage;
+    L.off_F = take(ns);
+    L.off_theta = take(fid_of(c) ? ns : 0);
+    L.off_region = take(size_t(L.n));
+    for (int b = 0; b < 2; ++b) {
+        L.off_rho[b] = take(size_t(L.n) * 8);
+        L.off_re[b] = take(fid_of(c) ? ns : 0);
+        L.off_im[b] = take(fid_of(c) ? ns : 0);
+        for (int a = 0; a < 3; ++a) {
+            L.off_m1[b][a] = take(msd_of(c) ? ns : 0);
+            L.off_m2[b][a] = take(msd_of(c) ? ns : 0);
+        }
+    }
+    size_t partial_bytes = size_t(per_step) * size_t(L.chunk);
+    if (partial_bytes < 4096 * 8)
+        partial_bytes = 4096 * 8;
+    L.off_partials = take(partial_bytes);
+    L.off_records = take(size_t(c.max_records) * L.K * 8);
+    L.off_staging = take(size_t(L.staging) * 8);
+    L.off_scalars = take(kScalars * 8);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+struct lpc_lattice {
+    lpc_config cfg{};
+    Layout L;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    char *arena = nullptr;
+    lpc::StateView st[2]{};
+    int cur = 0;
+    bool initialized = false;
+    int64_t steps_done = 0;
+    double Fmin = 0.0;
+
+    template <typename T = void>
+    T *at(size_t off) const
+    {
+        return reinterpret_cast<T *>(arena + off);
+    }
+    double *partials() const { return at<double>(L.off_partials); }
+    double *records() const { return at<double>(L.off_records); }
+    double *staging() const { return at<double>(L.off_staging); }
+    double *scalars() const { return at<double>(L.off_scalars); }
+
+    lpc::StepArgs args(int src) const
+    {
+        lpc::StepArgs a{};
+        a.g = {cfg.n[0], cfg.n[1], cfg.n[2], {cfg.bc[0], cfg.bc[1], cfg.bc[2]}};
+        a.precision = cfg.precision;
+        a.track = cfg.track;
+        a.R = cfg.n_regions;
+        a.K = L.K;
+        a.p0 = cfg.p_hop;
+        a.F = at(L.off_F);
+        a.theta = at(L.off_theta);
+        a.region = at<uint8_t>(L.off_region);
+        a.src = st[src];
+        a.dst = st[1 - src];
+        a.partials = partials();
+        return a;
+    }
+};
+
+namespace {
+
+lpc_status use_device(const lpc_lattice *lat)
+{
+    int d = -1;
+    LPC_HIP(hipGetDevice(&d));
+    if (d != lat->device)
+        LPC_HIP(hipSetDevice(lat->device));
+    return LPC_OK;
+}
+
+lpc_status check_sites(const lpc_lattice *lat, const void *p, int64_t n)
+{
+    if (!p)
+        return fail(LPC_ERR_ARG, "array is NULL");
+    if (n != lat->L.n)
+        return fail(LPC_ERR_ARG, "array has %lld values, lattice has %lld sites", (long long)n,
+                    (long long)lat->L.n);
+    return LPC_OK;
+}
+
+// Host doubles -> device field through the staging chunk, converted by a kernel.
+lpc_status upload_field(lpc_lattice *lat, const double *src, void *dst, double scale)
+{
+    const int64_t n = lat->L.n, chunk = lat->L.staging;
+    const size_t es = lat->L.storage;
+    for (int64_t o = 0; o < n; o += chunk) {
+        const int64_t c = n - o < chunk ? n - o : chunk;
+        LPC_HIP(hipMemcpyAsync(lat->staging(), src + o, size_t(c) * 8, hipMemcpyHostToDevice,
+                               lat->stream));
+        LPC_HIP(lpc::launch_store_field(lat->cfg.precision, lat->staging(),
+                                        static_cast<char *>(dst) + size_t(o) * es, c, scale,
+                                        lat->stream));
+    }
+    LPC_HIP(hipStreamSynchronize(lat->stream));
+    return LPC_OK;
+}
+
+lpc_status sync(lpc_lattice *lat)
+{
+    LPC_HIP(hipStreamSynchronize(lat->stream));
+    return LPC_OK;
+}
+
+lpc_status fetch_records(lpc_lattice *lat, std::vector<double> &rec)
+{
+    if (!lat->initialized)
+        return fail(LPC_ERR_STATE, "state not initialised");
+    if (lpc_status s = sync(lat))
+        return s;
+    const int64_t rows = lat->steps_done + 1;
+    rec.resize(size_t(rows) * lat->L.K);
+    LPC_HIP(hipMemcpy(rec.data(), lat->records(), rec.size() * 8, hipMemcpyDeviceToHost));
+    return LPC_OK;
+}
+
+lpc_status health(const lpc_lattice *lat, const std::vector<double> &rec)
+{
+    const int K = lat->L.K, R = lat->cfg.n_regions;
+    const int64_t rows = int64_t(rec.size()) / K;
+    double m0 = 0.0;
+    for (int r = 0; r < R; ++r)
+        m0 += rec[2 * R + r];
+    for (int64_t t = 0; t < rows; ++t) {
+        const double *row = rec.data() + t * K;
+        double mass = 0.0;
+        for (int r = 0; r < R; ++r) {
+            if (!std::isfinite(row[2 * r]) || !std::isfinite(row[2 * r + 1]))
+                return fail(LPC_ERR_NONFINITE, "FID is not finite at step %lld", (long long)t);
+            mass += row[2 * R + r];
+        }
+        if (!std::isfinite(mass))
+            return fail(LPC_ERR_NONFINITE, "total population is not finite at step %lld",
+                        (long long)t);
+        const double tol = lat->cfg.conservation_tol;
+        if (tol > 0.0 && m0 != 0.0 && std::fabs(mass - m0) > tol * std::fabs(m0))
+            return fail(LPC_ERR_CONSERVATION,
+                        "total population drifted by %.3e (relative) at step %lld, tolerance %.1e",
+                        std::fabs(mass - m0) / std::fabs(m0), (long long)t, tol);
+    }
+    return LPC_OK;
+}
+
+lpc_status write_initial_record(lpc_lattice *lat)
+{
+    lpc::StepArgs a = lat->args(lat->cur);
+    LPC_HIP(lpc::launch_record(lat->L.plan, a, lat->stream));
+    LPC_HIP(lpc::launch_finalize(lat->partials(), lat->L.plan.nblocks, lat->L.K, 1, lat->records(),
+                                 lat->stream));
+    return LPC_OK;
+}
+
+struct SaveHeader {
+    char magic[8];
+    uint32_t version;
+    int32_t n[3];
+    int32_t precision;
+    uint32_t track;
+    int32_t n_regions;
+    int32_t pad;
+    int64_t steps_done;
+    int64_t rows;
+};
+
+size_t state_bytes(const lpc_lattice *lat)
+{
+    const int64_t n = lat->L.n;
+    size_t b = size_t(n) * 8;
+    if (fid_of(lat->cfg))
+        b += 2 * size_t(n) * lat->L.storage;
+    if (msd_of(lat->cfg))
+        b += 6 * size_t(n) * lat->L.storage;
+    return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+lpc_status lpc_config_default(lpc_config *cfg, int32_t n)
+{
+    if (!cfg)
+        return fail(LPC_ERR_ARG, "config is NULL");
+    std::memset(cfg, 0, sizeof *cfg);
+    for (int a = 0; a < 3; ++a) {
+        cfg->n[a] = n;
+        cfg->bc[a] = LPC_BC_PERIODIC;
+    }
+    cfg->precision = LPC_PREC_FP64;
+    cfg->track = LPC_TRACK_FID | LPC_TRACK_MSD;
+    cfg->n_regions = 1;
+    cfg->p_hop = 1.0 / 7.0;
+    cfg->dt_s = 5e-6;
+    cfg->larmor_hz = 400e6;
+    cfg->spacing_m = 0.5e-9;
+    cfg->max_records = 1;
+    cfg->conservation_tol = 1e-12;
+    return ok();
+}
+
+lpc_status lpc_query_footprint(const lpc_config *cfg, size_t *bytes)
+{
+    if (lpc_status s = validate_config(cfg))
+        return s;
+    if (!bytes)
+        return fail(LPC_ERR_ARG, "bytes is NULL");
+    *bytes = plan_layout(*cfg).total;
+    return ok();
+}
+
+lpc_status lpc_create(const lpc_config *cfg, void *arena, size_t arena_bytes, void *stream,
+                      lpc_lattice **out)
+{
+    if (lpc_status s = validate_config(cfg))
+        return s;
+    if (!arena || !out)
+        return fail(LPC_ERR_ARG, "arena and out must not be NULL");
+    if (reinterpret_cast<uintptr_t>(arena) % kAlign)
+        return fail(LPC_ERR_ARG, "arena must be %zu-byte aligned", kAlign);
+    Layout L = plan_layout(*cfg);
+    if (arena_bytes < L.total)
+        return fail(LPC_ERR_OOM, "arena has %zu bytes, lattice needs %zu", arena_bytes, L.total);
+    auto *lat = new (std::nothrow) lpc_lattice;
+    if (!lat)
+        return fail(LPC_ERR_OOM, "host allocation failed");
+    lat->cfg = *cfg;
+    lat->L = L;
+    lat->stream = static_cast<hipStream_t>(stream);
+    lat->arena = static_cast<char *>(arena);
+    if (hipGetDevice(&lat->device) != hipSuccess) {
+        delete lat;
+        return fail(LPC_ERR_DEVICE, "hipGetDevice failed");
+    }
+    for (int b = 0; b < 2; ++b) {
+        lpc::StateView &v = lat->st[b];
+        v.rho = lat->at<double>(L.off_rho[b]);
+        v.re = fid_of(*cfg) ? lat->at(L.off_re[b]) : nullptr;
+        v.im = fid_of(*cfg) ? lat->at(L.off_im[b]) : nullptr;
+        for (int a = 0; a < 3; ++a) {
+            v.m1[a] = msd_of(*cfg) ? lat->at(L.off_m1[b][a]) : nullptr;
+            v.m2[a] = msd_of(*cfg) ? lat->at(L.off_m2[b][a]) : nullptr;
+        }
+    }
+    const size_t ns = size_t(L.n) * L.storage;
+    hipError_t e = hipMemsetAsync(lat->at(L.off_F), 0, ns, lat->stream);
+    if (e == hipSuccess && fid_of(*cfg))
+        e = hipMemsetAsync(lat->at(L.off_theta), 0, ns, lat->stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(lat->at(L.off_region), 0, size_t(L.n), lat->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(lat->stream);
+    if (e != hipSuccess) {
+        delete lat;
+        return fail(LPC_ERR_DEVICE, "clearing fields failed: %s", hipGetErrorString(e));
+    }
+    *out = lat;
+    return ok();
+}
+
+lpc_status lpc_destroy(lpc_lattice *lat)
+{
+    if (!lat)
+        return fail(LPC_ERR_ARG, "lattice is NULL");
+    (void)hipStreamSynchronize(lat->stream);
+    delete lat;
+    return ok();
+}
+
+lpc_status lpc_set_free_energy(lpc_lattice *lat, const double *F_kT, int64_t n)
+{
+    if (!lat)
+        return fail(LPC_ERR_ARG, "lattice is NULL");
+    if (lpc_status s = check_sites(lat, F_kT, n))
+        return s;
+    double fmin = INFINITY;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!std::isfinite(F_kT[i]))
+            return fail(LPC_ERR_NONFINITE, "F[%lld] is not finite", (long long)i);
+        fmin = F_kT[i] < fmin ? F_kT[i] : fmin;
+    }
+    if (lpc_status s = use_device(lat))
+        return s;
+    if (lpc_status s = upload_field(lat, F_kT, lat->at(lat->L.off_F), 1.0))
+        return s;
+    lat->Fmin = fmin;
+    return ok();
+}
+
+lpc_status lpc_set_shift(lpc_lattice *lat, const double *delta_ppm, int64_t n)
+{
+    if (!lat)
+        return fail(LPC_ERR_ARG, "lattice is NULL");
+    if (lpc_status s = check_sites(lat, delta_ppm, n))
+        return s;
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(delta_ppm[i]))
+            return fail(LPC_ERR_NONFINITE, "delta[%lld] is not finite", (long long)i);
+    if (!fid_of(lat->cfg))
+        return ok();  // no magnetisation tracked: the shift is not used
+    if (lpc_status s = use_device(lat))
+        return s;
+    // phase per step of Eq. (11): theta = 2 pi delta 1e-6 nu0 dt
+    const double scale = 2.0 * M_PI * 1e-6 * lat->cfg.larmor_hz * lat->cfg.dt_s;
+    return upload_field(lat, delta_ppm, lat->at(lat->L.off_theta), scale);
+}
+
+lpc_status lpc_set_regions(lpc_lattice *lat, const uint8_t *region, int64_t n)
+{
+    if (!lat)
+        return fail(LPC_ERR_ARG, "lattice is NULL");
+    if (lpc_status s = check_sites(lat, region, n))
+        return s;
+    for (int64_t i = 0; i < n; ++i)
+        if (region[i] >= lat->cfg.n_regions)
+            return fail(LPC_ERR_ARG, "region[%lld] = %d is not below n_regions = %d", (long long)i,
+                        int(region[i]), lat->cfg.n_regions);
+    if (lpc_status s = use_device(lat))
+        return s;
+    LPC_HIP(hipMemcpyAsync(lat->at(lat->L.off_region), region, size_t(n), hipMemcpyHostToDevice,
+                           lat->stream));
+    return sync(lat);
+}
+
+lpc_status lpc_init_state(lpc_lattice *lat, int32_t mode, const double *rho, int64_t n)
+{
+    if (!lat)
+        return fail(LPC_ERR_ARG, "lattice is NULL");
+    if (mode != LPC_INIT_UNIFORM && mode != LPC_INIT_BOLTZMANN && mode != LPC_INIT_USER)
+        return fail(LPC_ERR_ARG, "init mode %d unknown", mode);
+    if (mode == LPC_INIT_USER) {
+        if (lpc_status s = check_sites(lat, rho, n))
+            return s;
+        for (int64_t i = 0; i < n; ++i)
+            if (!std::isfinite(rho[i]))
+                return fail(LPC_ERR_NONFINITE, "rho[%lld] is not finite", (long long)i);
+    }
+    if (lpc_status s = use_device(lat))
+        return s;
+    if (lpc_status s = sync(lat))
+        return s;
+    lat->cur = 0;
+    const lpc::StateView &st = lat->st[0];
+    const int64_t N = lat->L.n;
+    if (mode == LPC_INIT_UNIFORM) {
+        LPC_HIP(lpc::launch_init_state(lat->cfg.precision, lat->cfg.track, st, nullptr, N,
+                                       lat->stream));
+    } else if (mode == LPC_INIT_BOLTZMANN) {
+        // Eq. (2): rho_i = N exp(-F_i) / sum_j exp(-F_j); weights relative to min F
+        int64_t nb = 0;
+        LPC_HIP(lpc::launch_boltzmann_weights(lat->cfg.precision, lat->at(lat->L.off_F), lat->Fmin,
+                                              st.rho, N, lat->partials(), &nb, lat->stream));
+        LPC_HIP(lpc::launch_finalize(lat->partials(), nb, 1, 1, lat->scalars(), lat->stream));
+        LPC_HIP(lpc::launch_boltzmann_scale(st.rho, N, double(N), lat->scalars(), lat->stream));
+        LPC_HIP(lpc::launch_init_state(lat->cfg.precision, lat->cfg.track, st, st.rho, N,
+                                       lat->stream));
+    } else {
+        LPC_HIP(hipMemcpyAsync(st.rho, rho, size_t(N) * 8, hipMemcpyHostToDevice, lat->stream));
+        LPC_HIP(lpc::launch_init_state(lat->cfg.precision, lat->cfg.track, st, st.rho, N,
+                                       lat->stream));
+    }
+    lat->steps_done = 0;
+    if (lpc_status s = write_initial_record(lat))
+        return s;
+    if (lpc_status s = sync(lat))
+        return s;
+    lat->initialized = true;
+    return ok();
+}
+
+lpc_status lpc_run(lpc_lattice *lat, int64_t n_steps)
+{
+    if (!lat)
+        return fail(LPC_ERR_ARG, "lattice is NULL");
+    if (n_steps < 0)
+        return fail(LPC_ERR_ARG, "n_steps = %lld is negative", (long long)n_steps);
+    if (!lat->initialized)
+        return fail(LPC_ERR_STATE, "lpc_init_state or lpc_load_state must come first");
+    if (lat->steps_done + n_steps > lat->cfg.max_records - 1)
+        return fail(LPC_ERR_STATE, "records hold %lld steps; %lld done, %lld requested",
+                    (long long)(lat->cfg.max_records - 1), (long long)lat->steps_done,
+                    (long long)n_steps);
+    if (lpc_status s = use_device(lat))
+        return s;
+    const lpc::SweepPlan &plan = lat->L.plan;
+    const int K = lat->L.K;
+    int64_t left = n_steps;
+    while (left > 0) {
+        const int64_t c = left < lat->L.chunk ? left : lat->L.chunk;
+        for (int64_t s = 0; s < c; ++s) {
+            lpc::StepArgs a = lat->args(lat->cur);
+            a.partials = lat->partials() + s * K * plan.nblocks;
+            LPC_HIP(lpc::launch_step(plan, a, lat->stream));
+            lat->cur ^= 1;
+        }
+        LPC_HIP(lpc::launch_finalize(lat->partials(), plan.nblocks, K, c,
+                                     lat->records() + (lat->steps_done + 1) * K, lat->stream));
+        lat->steps_done += c;
+        left -= c;
+    }
+    return ok();
+}
+
+lpc_status lpc_synchronize(lpc_lattice *lat)
+{
+    if (!lat)
+        return fail(LPC_ERR_ARG, "lattice is NULL");
+    return sync(lat);
+}
+
+lpc_status lpc_steps_done(const lpc_lattice *lat, int64_t *n)
+{
+    if (!lat || !n)
+        return fail(LPC_ERR_ARG, "NULL argument");
+    *n = lat->steps_done;
+    return ok();
+}
+
+lpc_status lpc_record_width(const lpc_lattice *lat, int32_t *K)
+{
+    if (!lat || !K)
+        return fail(LPC_ERR_ARG, "NULL argument");
+    *K = lat->L.K;
+    return ok();
+}
+
+lpc_status lpc_read_records(lpc_lattice *lat, double *records, int64_t cap_rows, int64_t *rows)
+{
+    if (!lat || !records || !rows)
+        return fail(LPC_ERR_ARG, "NULL argument");
+    std::vector<double> rec;
+    if (lpc_status s = fetch_records(lat, rec))
+        return s;
+    const int64_t r = lat->steps_done + 1;
+    if (cap_rows < r)
+        return fail(LPC_ERR_OOM, "records need %lld rows, buffer has %lld", (long long)r,
+                    (long long)cap_rows);
+    std::memcpy(records, rec.data(), rec.size() * 8);
+    *rows = r;
+    return ok();
+}
+
+lpc_status lpc_read_population(lpc_lattice *lat, double *rho, int64_t n)
+{
+    if (!lat)
+        return fail(LPC_ERR_ARG, "lattice is NULL");
+    if (lpc_status s = check_sites(lat, rho, n))
+        return s;
+    if (!lat->initialized)
+        return fail(LPC_ERR_STATE, "state not initialised");
+    if (lpc_status s = sync(lat))
+        return s;
+    LPC_HIP(hipMemcpy(rho, lat->st[lat->cur].rho, size_t(n) * 8, hipMemcpyDeviceToHost));
+    return ok();
+}
+
+lpc_status lpc_read_magnetization(lpc_lattice *lat, double *re, double *im, int64_t n)
+{
+    if (!lat)
+        return fail(LPC_ERR_ARG, "lattice is NULL");
+    if (lpc_status s = check_sites(lat, re, n))
+        return s;
+    if (lpc_status s = check_sites(lat, im, n))
+        return s;
+    if (!fid_of(lat->cfg))
+        return fail(LPC_ERR_STATE, "magnetisation is not tracked");
+    if (!lat->initialized)
+        return fail(LPC_ERR_STATE, "state not initialised");
+    if (lpc_status s = sync(lat))
+        return s;
+    const lpc::StateView &v = lat->st[lat->cur];
+    if (lat->L.storage == 8) {
+        LPC_HIP(hipMemcpy(re, v.re, size_t(n) * 8, hipMemcpyDeviceToHost));
+        LPC_HIP(hipMemcpy(im, v.im, size_t(n) * 8, hipMemcpyDeviceToHost));
+    } else {
+        std::vector<float> tmp(static_cast<size_t>(n));
+        LPC_HIP(hipMemcpy(tmp.data(), v.re, size_t(n) * 4, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < n; ++i)
+            re[i] = tmp[size_t(i)];
+        LPC_HIP(hipMemcpy(tmp.data(), v.im, size_t(n) * 4, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < n; ++i)
+            im[i] = tmp[size_t(i)];
+    }
+    return ok();
+}
+
+lpc_status lpc_check(lpc_lattice *lat)
+{
+    if (!lat)
+        return fail(LPC_ERR_ARG, "lattice is NULL");
+    std::vector<double> rec;
+    if (lpc_status s = fetch_records(lat, rec))
+        return s;
+    return health(lat, rec);
+}
+
+lpc_status lpc_read_fid(lpc_lattice *lat, int32_t region, double *re, double *im, int64_t cap,
+                        int64_t *len)
+{
+    if (!lat || !re || !im || !len)
+        return fail(LPC_ERR_ARG, "NULL argument");
+    const int R = lat->cfg.n_regions;
+    if (region < -1 || region >= R)
+        return fail(LPC_ERR_ARG, "region %d outside -1..%d", region, R - 1);
+    std::vector<double> rec;
+    if (lpc_status s = fetch_records(lat, rec))
+        return s;
+    if (lpc_status s = health(lat, rec))
+        return s;
+    const int64_t rows = lat->steps_done + 1;
+    if (cap < rows)
+        return fail(LPC_ERR_OOM, "FID has %lld samples, buffer holds %lld", (long long)rows,
+                    (long long)cap);
+    const int K = lat->L.K;
+    for (int64_t t = 0; t < rows; ++t) {
+        const double *row = rec.data() + t * K;
+        double a = 0.0, b = 0.0;
+        for (int r = 0; r < R; ++r) {
+            if (region >= 0 && r != region)
+                continue;
+            a += row[2 * r];
+            b += row[2 * r + 1];
+        }
+        re[t] = a;
+        im[t] = b;
+    }
+    *len = rows;
+    return ok();
+}
+
+lpc_status lpc_read_moments(lpc_lattice *lat, double *mass, double *msd_xyz, double *drift_xyz,
+                            int64_t cap, int64_t *len)
+{
+    if (!lat || !mass || !msd_xyz || !drift_xyz || !len)
+        return fail(LPC_ERR_ARG, "NULL argument");
+    std::vector<double> rec;
+    if (lpc_status s = fetch_records(lat, rec))
+        return s;
+    if (lpc_status s = health(lat, rec))
+        return s;
+    const int64_t rows = lat->steps_done + 1;
+    if (cap < rows)
+        return fail(LPC_ERR_OOM, "moments have %lld rows, buffer holds %lld", (long long)rows,
+                    (long long)cap);
+    const int K = lat->L.K, R = lat->cfg.n_regions;
+    for (int64_t t = 0; t < rows; ++t) {
+        const double *row = rec.data() + t * K;
+        double m = 0.0;
+        for (int r = 0; r < R; ++r)
+            m += row[2 * R + r];
+        mass[t] = m;
+        for (int a = 0; a < 3; ++a) {
+            drift_xyz[3 * t + a] = row[3 * R + a] / m;
+            msd_xyz[3 * t + a] = row[3 * R + 3 + a] / m;
+        }
+    }
+    *len = rows;
+    return ok();
+}
+
+lpc_status lpc_read_uptake(lpc_lattice *lat, double *per_step_per_region, int64_t cap,
+                           int64_t *len)
+{
+    if (!lat || !per_step_per_region || !len)
+        return fail(LPC_ERR_ARG, "NULL argument");
+    std::vector<double> rec;
+    if (lpc_status s = fetch_records(lat, rec))
+        return s;
+    if (lpc_status s = health(lat, rec))
+        return s;
+    const int64_t rows = lat->steps_done + 1;
+    if (cap < rows)
+        return fail(LPC_ERR_OOM, "uptake has %lld rows, buffer holds %lld", (long long)rows,
+                    (long long)cap);
+    const int K = lat->L.K, R = lat->cfg.n_regions;
+    for (int64_t t = 0; t < rows; ++t)
+        for (int r = 0; r < R; ++r)
+            per_step_per_region[t * R + r] = rec[size_t(t * K + 2 * R + r)];
+    *len = rows;
+    return ok();
+}
+
+lpc_status lpc_save_state(lpc_lattice *lat, void *buf, size_t cap, size_t *len)
+{
+    if (!lat || !len)
+        return fail(LPC_ERR_ARG, "NULL argument");
+    if (!lat->initialized)
+        return fail(LPC_ERR_STATE, "state not initialised");
+    const int64_t rows = lat->steps_done + 1;
+    const size_t need = sizeof(SaveHeader) + state_bytes(lat) + size_t(rows) * lat->L.K * 8;
+    if (!buf) {
+        *len = need;
+        return ok();
+    }
+    if (cap < need)
+        return fail(LPC_ERR_OOM, "checkpoint needs %zu bytes, buffer has %zu", need, cap);
+    if (lpc_status s = sync(lat))
+        return s;
+    SaveHeader h{};
+    std::memcpy(h.magic, "LPCSTATE", 8);
+    h.version = 1;
+    for (int a = 0; a < 3; ++a)
+        h.n[a] = lat->cfg.n[a];
+    h.precision = lat->cfg.precision;
+    h.track = lat->cfg.track;
+    h.n_regions = lat->cfg.n_regions;
+    h.steps_done = lat->steps_done;
+    h.rows = rows;
+    char *p = static_cast<char *>(buf);
+    std::memcpy(p, &h, sizeof h);
+    p += sizeof h;
+    const lpc::StateView &v = lat->st[lat->cur];
+    const size_t n = size_t(lat->L.n), ns = n * lat->L.storage;
+    LPC_HIP(hipMemcpy(p, v.rho, n * 8, hipMemcpyDeviceToHost));
+    p += n * 8;
+    if (fid_of(lat->cfg)) {
+        LPC_HIP(hipMemcpy(p, v.re, ns, hipMemcpyDeviceToHost));
+        p += ns;
+        LPC_HIP(hipMemcpy(p, v.im, ns, hipMemcpyDeviceToHost));
+        p += ns;
+    }
+    if (msd_of(lat->cfg)) {
+        for (int a = 0; a < 3; ++a) {
+            LPC_HIP(hipMemcpy(p, v.m1[a], ns, hipMemcpyDeviceToHost));
+            p += ns;
+        }
+        for (int a = 0; a < 3; ++a) {
+            LPC_HIP(hipMemcpy(p, v.m2[a], ns, hipMemcpyDeviceToHost));
+            p += ns;
+        }
+    }
+    LPC_HIP(hipMemcpy(p, lat->records(), size_t(rows) * lat->L.K * 8, hipMemcpyDeviceToHost));
+    *len = need;
+    return ok();
+}
+
+lpc_status lpc_load_state(lpc_lattice *lat, const void *buf, size_t len)
+{
+    if (!lat || !buf)
+        return fail(LPC_ERR_ARG, "NULL argument");
+    if (len < sizeof(SaveHeader))
+        return fail(LPC_ERR_ARG, "checkpoint too short");
+    SaveHeader h;
+    std::memcpy(&h, buf, sizeof h);
+    if (std::memcmp(h.magic, "LPCSTATE", 8) != 0 || h.version != 1)
+        return fail(LPC_ERR_ARG, "not a version-1 lattice checkpoint");
+    for (int a = 0; a < 3; ++a)
+        if (h.n[a] != lat->cfg.n[a])
+            return fail(LPC_ERR_ARG, "checkpoint shape differs from the lattice");
+    if (h.precision != lat->cfg.precision || h.track != lat->cfg.track ||
+        h.n_regions != lat->cfg.n_regions)
+        return fail(LPC_ERR_ARG, "checkpoint precision, track set or regions differ");
+    if (h.rows != h.steps_done + 1 || h.rows < 1 || h.rows > lat->cfg.max_records)
+        return fail(LPC_ERR_STATE, "checkpoint holds %lld records, lattice keeps %lld",
+                    (long long)h.rows, (long long)lat->cfg.max_records);
+    const size_t need = sizeof(SaveHeader) + state_bytes(lat) + size_t(h.rows) * lat->L.K * 8;
+    if (len < need)
+        return fail(LPC_ERR_ARG, "checkpoint has %zu bytes, needs %zu", len, need);
+    if (lpc_status s = use_device(lat))
+        return s;
+    if (lpc_status s = sync(lat))
+        return s;
+    const char *p = static_cast<const char *>(buf) + sizeof h;
+    lat->cur = 0;
+    const lpc::StateView &v = lat->st[0];
+    const size_t n = size_t(lat->L.n), ns = n * lat->L.storage;
+    LPC_HIP(hipMemcpy(v.rho, p, n * 8, hipMemcpyHostToDevice));
+    p += n * 8;
+    if (fid_of(lat->cfg)) {
+        LPC_HIP(hipMemcpy(v.re, p, ns, hipMemcpyHostToDevice));
+        p += ns;
+        LPC_HIP(hipMemcpy(v.im, p, ns, hipMemcpyHostToDevice));
+        p += ns;
+    }
+    if (msd_of(lat->cfg)) {
+        for (int a = 0; a < 3; ++a) {
+            LPC_HIP(hipMemcpy(v.m1[a], p, ns, hipMemcpyHostToDevice));
+            p += ns;
+        }
+        for (int a = 0; a < 3; ++a) {
+            LPC_HIP(hipMemcpy(v.m2[a], p, ns, hipMemcpyHostToDevice));
+            p += ns;
+        }
+    }
+    LPC_HIP(hipMemcpy(lat->records(), p, size_t(h.rows) * lat->L.K * 8, hipMemcpyHostToDevice));
+    lat->steps_done = h.steps_done;
+    lat->initialized = true;
+    return ok();
+}
+
+const char *lpc_last_error(void)
+{
+    return g_error.c_str();
+}
+
+const char *lpc_version(void)
+{
+    return "liblpc 0.1 (gfx950)";
+}
+
+}  // extern "C"

@@ -1,0 +1,213 @@
+"""Python face of liblpc: one simulated lattice on one GPU.
+
+A thin binding: it converts arguments, keeps the torch-allocated device arena alive and
+turns status codes into exceptions. Every step of the sweep runs in the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _native as N
+from ._native import LpcError  # noqa: F401  (re-exported)
+
+BC = {"periodic": N.BC_PERIODIC, "closed": N.BC_CLOSED}
+PRECISION = {"fp64": N.PREC_FP64, "mixed": N.PREC_MIXED}
+INIT = {"uniform": N.INIT_UNIFORM, "boltzmann": N.INIT_BOLTZMANN, "user": N.INIT_USER}
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def make_config(shape_xyz, bc=("periodic",) * 3, precision="fp64", track=("fid", "msd"),
+                n_regions=1, p_hop=1.0 / 7.0, dt_s=5e-6, larmor_hz=400e6, spacing_m=0.5e-9,
+                max_records=1, conservation_tol=1e-12) -> N.Config:
+    cfg = N.Config()
+    for a in range(3):
+        cfg.n[a] = int(shape_xyz[a])
+        b = bc[a]
+        cfg.bc[a] = BC[b] if isinstance(b, str) else int(b)
+    cfg.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    t = 0
+    for name in track:
+        t |= {"fid": N.TRACK_FID, "msd": N.TRACK_MSD}[name]
+    cfg.track = t
+    cfg.n_regions = int(n_regions)
+    cfg.reserved = 0
+    cfg.p_hop = float(p_hop)
+    cfg.dt_s = float(dt_s)
+    cfg.larmor_hz = float(larmor_hz)
+    cfg.spacing_m = float(spacing_m)
+    cfg.max_records = int(max_records)
+    cfg.conservation_tol = float(conservation_tol)
+    return cfg
+
+
+def footprint(cfg: N.Config) -> int:
+    b = ctypes.c_size_t()
+    N.call("lpc_query_footprint", ctypes.byref(cfg), ctypes.byref(b))
+    return int(b.value)
+
+
+class Lattice:
+    """A lattice of nx*ny*nz sites resident in one device arena.
+
+    shape_xyz: (nx, ny, nz); host arrays use shape (nz, ny, nx) (x fastest).
+    """
+
+    def __init__(self, shape_xyz, bc=("periodic",) * 3, precision="fp64", track=("fid", "msd"),
+                 n_regions=1, p_hop=1.0 / 7.0, dt_s=5e-6, larmor_hz=400e6, spacing_m=0.5e-9,
+                 max_records=1, conservation_tol=1e-12, device=None, stream=None):
+        self.cfg = make_config(shape_xyz, bc, precision, track, n_regions, p_hop, dt_s,
+                               larmor_hz, spacing_m, max_records, conservation_tol)
+        self.shape_xyz = tuple(int(v) for v in shape_xyz)
+        self.n_sites = int(np.prod(self.shape_xyz))
+        self.n_regions = int(n_regions)
+        self.track = tuple(track)
+        self.device = torch.device(device if device is not None else "cuda")
+        nbytes = footprint(self.cfg)
+        self.arena = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            N.call("lpc_create", ctypes.byref(self.cfg), ctypes.c_void_p(self.arena.data_ptr()),
+                   nbytes, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        self._h = h
+        K = ctypes.c_int32()
+        N.call("lpc_record_width", self._h, ctypes.byref(K))
+        self.K = int(K.value)
+
+    # -------------------------------------------------------------- lifetime
+    @property
+    def handle(self):
+        if self._h is None:
+            raise N.LpcError(N.LPC_ERR_STATE, "lattice is closed")
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            N.call("lpc_destroy", self._h)
+            self._h = None
+            self.arena = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -------------------------------------------------------------- inputs
+    def _sites(self, a, dtype):
+        a = np.ascontiguousarray(a, dtype=dtype).reshape(-1)
+        return a
+
+    def set_free_energy(self, F_kT):
+        a = self._sites(F_kT, np.float64)
+        N.call("lpc_set_free_energy", self.handle, _ptr(a), a.size)
+
+    def set_shift(self, delta_ppm):
+        a = self._sites(delta_ppm, np.float64)
+        N.call("lpc_set_shift", self.handle, _ptr(a), a.size)
+
+    def set_regions(self, region):
+        a = self._sites(region, np.uint8)
+        N.call("lpc_set_regions", self.handle, _ptr(a), a.size)
+
+    def set_fields(self, fields):
+        """Free energy, shift and regions from a synth.Fields-like object."""
+        self.set_free_energy(fields.F)
+        self.set_shift(fields.delta)
+        self.set_regions(fields.region)
+
+    def init_state(self, mode="uniform", rho=None):
+        if rho is not None:
+            a = self._sites(rho, np.float64)
+            N.call("lpc_init_state", self.handle, INIT["user"], _ptr(a), a.size)
+        else:
+            N.call("lpc_init_state", self.handle, INIT[mode], None, 0)
+
+    # -------------------------------------------------------------- stepping
+    def run(self, n_steps: int):
+        N.call("lpc_run", self.handle, int(n_steps))
+
+    def synchronize(self):
+        N.call("lpc_synchronize", self.handle)
+
+    @property
+    def steps_done(self) -> int:
+        v = ctypes.c_int64()
+        N.call("lpc_steps_done", self.handle, ctypes.byref(v))
+        return int(v.value)
+
+    # -------------------------------------------------------------- outputs
+    def records(self) -> np.ndarray:
+        rows = self.steps_done + 1
+        out = np.empty((rows, self.K))
+        got = ctypes.c_int64()
+        N.call("lpc_read_records", self.handle, _ptr(out), rows, ctypes.byref(got))
+        return out[:got.value]
+
+    def population(self) -> np.ndarray:
+        out = np.empty(self.n_sites)
+        N.call("lpc_read_population", self.handle, _ptr(out), out.size)
+        nx, ny, nz = self.shape_xyz
+        return out.reshape(nz, ny, nx)
+
+    def magnetization(self) -> np.ndarray:
+        re = np.empty(self.n_sites)
+        im = np.empty(self.n_sites)
+        N.call("lpc_read_magnetization", self.handle, _ptr(re), _ptr(im), re.size)
+        nx, ny, nz = self.shape_xyz
+        return (re + 1j * im).reshape(nz, ny, nx)
+
+    def fid(self, region=None) -> np.ndarray:
+        rows = self.steps_done + 1
+        re = np.empty(rows)
+        im = np.empty(rows)
+        got = ctypes.c_int64()
+        N.call("lpc_read_fid", self.handle, -1 if region is None else int(region), _ptr(re),
+               _ptr(im), rows, ctypes.byref(got))
+        return (re + 1j * im)[:got.value]
+
+    def moments(self):
+        """(mass[rows], msd[rows, 3], drift[rows, 3]) in lattice units."""
+        rows = self.steps_done + 1
+        mass = np.empty(rows)
+        msd = np.empty((rows, 3))
+        drift = np.empty((rows, 3))
+        got = ctypes.c_int64()
+        N.call("lpc_read_moments", self.handle, _ptr(mass), _ptr(msd), _ptr(drift), rows,
+               ctypes.byref(got))
+        return mass, msd, drift
+
+    def uptake(self) -> np.ndarray:
+        rows = self.steps_done + 1
+        out = np.empty((rows, self.n_regions))
+        got = ctypes.c_int64()
+        N.call("lpc_read_uptake", self.handle, _ptr(out), rows, ctypes.byref(got))
+        return out
+
+    def check(self):
+        N.call("lpc_check", self.handle)
+
+    # -------------------------------------------------------------- checkpoints
+    def save_state(self) -> bytes:
+        need = ctypes.c_size_t()
+        N.call("lpc_save_state", self.handle, None, 0, ctypes.byref(need))
+        buf = (ctypes.c_char * need.value)()
+        got = ctypes.c_size_t()
+        N.call("lpc_save_state", self.handle, buf, need.value, ctypes.byref(got))
+        return bytes(buf[:got.value])
+
+    def load_state(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        N.call("lpc_load_state", self.handle, buf, len(blob))

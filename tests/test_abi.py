@@ -1,0 +1,102 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every function that
+include/lpc.h declares, and validates configurations before touching the device."""
+import ctypes
+import os
+
+import pytest
+
+from paper_2603_22553_amd import _native as N
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(N.LIB_PATH):
+        from paper_2603_22553_amd import build
+        build.build()
+    return N.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = N.declared_symbols()
+    assert "lpc_run" in names and "lpc_create" in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, f"declared but not exported: {missing}"
+    # every declared call has a binding signature (or is one of the string getters)
+    unbound = [n for n in names if n not in N.SIGNATURES and n not in ("lpc_last_error", "lpc_version")]
+    assert not unbound
+
+
+def test_version_string(lib):
+    assert b"gfx950" in lib.lpc_version()
+
+
+def _cfg(side=8, **kw):
+    c = N.Config()
+    N.call("lpc_config_default", ctypes.byref(c), side)
+    for k, v in kw.items():
+        if k in ("n", "bc"):
+            for a in range(3):
+                getattr(c, k)[a] = v[a]
+        else:
+            setattr(c, k, v)
+    return c
+
+
+def _footprint(c):
+    b = ctypes.c_size_t()
+    st = N.status("lpc_query_footprint", ctypes.byref(c), ctypes.byref(b))
+    return st, b.value
+
+
+def test_default_config(lib):
+    c = _cfg(16)
+    assert list(c.n) == [16, 16, 16] and list(c.bc) == [0, 0, 0]
+    assert abs(c.p_hop - 1 / 7) < 1e-16 and c.dt_s == 5e-6 and c.larmor_hz == 400e6
+    st, b = _footprint(c)
+    assert st == N.LPC_OK and b > 0
+
+
+def test_footprint_byte_model(lib):
+    """The arena holds fields and two state buffers of the track set: it grows with sites,
+    records and precision, and the mixed path stores the float arrays in half the space."""
+    n = 64
+    sites = n ** 3
+    st, fp64 = _footprint(_cfg(n, max_records=1))
+    st2, mixed = _footprint(_cfg(n, max_records=1, precision=N.PREC_MIXED))
+    assert st == st2 == N.LPC_OK
+    # per site: F, theta, region, 2 x (rho + 2 m + 6 moments); mixed: float F/theta/m/moments
+    assert fp64 >= sites * (8 + 8 + 1 + 2 * 9 * 8)
+    assert mixed >= sites * (4 + 4 + 1 + 2 * (8 + 8 * 4))
+    assert mixed < fp64
+    _, more = _footprint(_cfg(n, max_records=100001))
+    assert more - fp64 >= 100000 * (3 + 6) * 8
+    _, fid_only = _footprint(_cfg(n, track=N.TRACK_FID))
+    assert fid_only < fp64
+
+
+@pytest.mark.parametrize("field,value", [
+    ("p_hop", 0.2), ("p_hop", -0.01), ("n_regions", 0), ("n_regions", 9), ("max_records", 0),
+    ("precision", 5), ("track", 8), ("dt_s", 0.0), ("reserved", 1), ("conservation_tol", -1.0),
+])
+def test_config_rejected(lib, field, value):
+    st, _ = _footprint(_cfg(8, **{field: value}))
+    assert st == N.LPC_ERR_ARG
+    assert len(lib.lpc_last_error()) > 0
+
+
+def test_bad_shape_rejected(lib):
+    st, _ = _footprint(_cfg(8, n=(0, 4, 4)))
+    assert st == N.LPC_ERR_ARG
+    st, _ = _footprint(_cfg(8, bc=(0, 2, 0)))
+    assert st == N.LPC_ERR_ARG
+
+
+def test_null_arguments(lib):
+    assert N.status("lpc_query_footprint", None, None) == N.LPC_ERR_ARG
+    assert N.status("lpc_destroy", None) == N.LPC_ERR_ARG
+    assert N.status("lpc_run", None, 1) == N.LPC_ERR_ARG
+
+
+def test_max_p_hop_accepted(lib):
+    st, _ = _footprint(_cfg(4, p_hop=1.0 / 6.0))
+    assert st == N.LPC_OK

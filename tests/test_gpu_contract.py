@@ -1,0 +1,169 @@
+"""GPU-side contract of the C-ABI: error codes, ownership, determinism, checkpoints."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2603_22553_amd import _native as N
+from paper_2603_22553_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def lattice(shape=(12, 10, 8), **kw):
+    from paper_2603_22553_amd.lattice import Lattice
+    kw.setdefault("max_records", 201)
+    return Lattice(shape, **kw)
+
+
+def test_error_codes():
+    f = synth.random_fields((12, 10, 8), seed=1, n_regions=2)
+    with lattice(n_regions=2) as lat:
+        # run before init
+        with pytest.raises(N.LpcError) as e:
+            lat.run(1)
+        assert e.value.status == N.LPC_ERR_STATE
+        # wrong number of values
+        with pytest.raises(N.LpcError) as e:
+            lat.set_free_energy(np.zeros(10))
+        assert e.value.status == N.LPC_ERR_ARG
+        # non-finite input
+        bad = f.F.copy()
+        bad[3, 2, 1] = np.nan
+        with pytest.raises(N.LpcError) as e:
+            lat.set_free_energy(bad)
+        assert e.value.status == N.LPC_ERR_NONFINITE
+        bad = f.delta.copy()
+        bad[0, 0, 0] = np.inf
+        with pytest.raises(N.LpcError) as e:
+            lat.set_shift(bad)
+        assert e.value.status == N.LPC_ERR_NONFINITE
+        # region id out of range
+        reg = f.region.copy()
+        reg[1, 1, 1] = 2
+        with pytest.raises(N.LpcError) as e:
+            lat.set_regions(reg)
+        assert e.value.status == N.LPC_ERR_ARG
+        lat.set_fields(f)
+        lat.init_state("uniform")
+        lat.run(150)
+        # record capacity: 200 steps fit, 201 do not
+        with pytest.raises(N.LpcError) as e:
+            lat.run(51)
+        assert e.value.status == N.LPC_ERR_STATE
+        lat.run(50)
+        assert lat.steps_done == 200
+        with pytest.raises(N.LpcError) as e:
+            lat.fid(region=2)
+        assert e.value.status == N.LPC_ERR_ARG
+        with pytest.raises(N.LpcError) as e:
+            lat.init_state(rho=np.full(f.n_sites, np.nan))
+        assert e.value.status == N.LPC_ERR_NONFINITE
+
+
+def test_arena_too_small_and_misaligned():
+    from paper_2603_22553_amd.lattice import make_config, footprint
+    cfg = make_config((8, 8, 8), max_records=10)
+    need = footprint(cfg)
+    buf = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+    h = ctypes.c_void_p()
+    st = N.status("lpc_create", ctypes.byref(cfg), ctypes.c_void_p(buf.data_ptr()), need - 1,
+                  None, ctypes.byref(h))
+    assert st == N.LPC_ERR_OOM
+    st = N.status("lpc_create", ctypes.byref(cfg), ctypes.c_void_p(buf.data_ptr() + 8), need,
+                  None, ctypes.byref(h))
+    assert st == N.LPC_ERR_ARG
+
+
+def test_arena_is_borrowed():
+    """The library never frees the arena: it stays a valid torch tensor after destroy."""
+    lat = lattice()
+    arena = lat.arena
+    lat.set_fields(synth.random_fields((12, 10, 8), seed=2))
+    lat.init_state()
+    lat.run(10)
+    lat.close()
+    arena.fill_(7)
+    torch.cuda.synchronize()
+    assert int(arena[0].item()) == 7
+
+
+def _run(f, steps, **kw):
+    with lattice(f.shape_xyz, n_regions=f.n_regions, **kw) as lat:
+        lat.set_fields(f)
+        lat.init_state()
+        lat.run(steps)
+        return lat.records(), lat.population()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_bitwise_determinism(precision):
+    f = synth.random_fields((40, 24, 19), seed=9, n_regions=3)
+    a = _run(f, 200, precision=precision)
+    b = _run(f, 200, precision=precision)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_checkpoint_restart_bitwise(precision):
+    """N + M steps straight equal N steps, save, load into a fresh lattice, M steps."""
+    f = synth.random_fields((20, 18, 16), seed=11, n_regions=2)
+    full_rec, full_rho = _run(f, 120, precision=precision)
+    with lattice(f.shape_xyz, n_regions=2, precision=precision) as a:
+        a.set_fields(f)
+        a.init_state()
+        a.run(50)
+        blob = a.save_state()
+    with lattice(f.shape_xyz, n_regions=2, precision=precision) as b:
+        b.set_fields(f)
+        b.load_state(blob)
+        assert b.steps_done == 50
+        b.run(70)
+        assert np.array_equal(b.records(), full_rec)
+        assert np.array_equal(b.population(), full_rho)
+
+
+def test_checkpoint_mismatch_rejected():
+    with lattice((8, 8, 8)) as a:
+        a.set_fields(synth.random_fields((8, 8, 8), seed=1))
+        a.init_state()
+        blob = a.save_state()
+    with lattice((8, 8, 9)) as b:
+        with pytest.raises(N.LpcError) as e:
+            b.load_state(blob)
+        assert e.value.status == N.LPC_ERR_ARG
+
+
+def test_conservation_alarm_from_host_state():
+    """A hand-made state whose recorded mass jumps makes the next read report it."""
+    f = synth.random_fields((8, 8, 8), seed=3)
+    with lattice((8, 8, 8)) as a:
+        a.set_fields(f)
+        a.init_state()
+        a.run(5)
+        blob = bytearray(a.save_state())
+    # records are the tail of the checkpoint: scale the population entry of the last row
+    K = 3 * 1 + 6
+    tail = np.frombuffer(bytes(blob[-6 * K * 8:]), dtype=np.float64).copy().reshape(6, K)
+    tail[-1, 2] *= 1.0 + 1e-9
+    blob[-6 * K * 8:] = tail.tobytes()
+    with lattice((8, 8, 8)) as b:
+        b.set_fields(f)
+        b.load_state(bytes(blob))
+        with pytest.raises(N.LpcError) as e:
+            b.fid()
+        assert e.value.status == N.LPC_ERR_CONSERVATION
+        b.records()   # raw records stay readable
+
+
+def test_streams_and_async():
+    """lpc_run only queues work on the lattice's stream; reads synchronize it."""
+    s = torch.cuda.Stream()
+    f = synth.random_fields((32, 32, 32), seed=4)
+    with lattice((32, 32, 32), stream=s, max_records=1001) as lat:
+        lat.set_fields(f)
+        lat.init_state()
+        lat.run(1000)
+        rec = lat.records()
+        assert rec.shape[0] == 1001 and np.all(np.isfinite(rec))
