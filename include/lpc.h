@@ -59,9 +59,10 @@ typedef enum lpc_status {
 
 enum { LPC_BC_PERIODIC = 0, LPC_BC_CLOSED = 1 };
 
-/* FP64: every field and state array in double. MIXED: populations in double, free
- * energy, phase and the magnetisation / moment arrays stored in float; all arithmetic
- * of the update and every record sum in double. */
+/* FP64: every field, state array and operation in double. MIXED: populations stored
+ * and updated in double; free energy, phase, magnetisation and moments stored and
+ * updated in float (hop probabilities in float, promoted for the population update);
+ * every record sum in double. */
 enum { LPC_PREC_FP64 = 0, LPC_PREC_MIXED = 1 };
 
 /* Track set. Populations are always propagated. */
@@ -148,6 +149,16 @@ lpc_status lpc_check(lpc_lattice *lat);
  * the same configuration; fields are not part of the checkpoint. */
 lpc_status lpc_save_state(lpc_lattice *lat, void *buf, size_t cap, size_t *len);
 lpc_status lpc_load_state(lpc_lattice *lat, const void *buf, size_t len);
+
+/* Calibration utility: copies `bytes` bytes from device buffer src to device buffer dst
+ * (16-byte aligned, non-overlapping) with a plain streaming kernel on `stream`, so that
+ * achieved HBM bandwidth and hardware traffic counters can be compared with a kernel of
+ * known traffic (bytes read + bytes written = 2 * bytes). Asynchronous. */
+lpc_status lpc_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
+
+/* Launch plan of the sweep as text (tile shape, z-chunk, workgroups, steps finalised
+ * together), NUL-terminated and truncated to cap bytes. */
+lpc_status lpc_describe(const lpc_lattice *lat, char *buf, size_t cap);
 
 const char *lpc_last_error(void);
 const char *lpc_version(void);

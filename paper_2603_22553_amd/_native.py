@@ -78,6 +78,8 @@ SIGNATURES = {
     "lpc_check": [_P],
     "lpc_save_state": [_P, _P, _SZ, _PSZ],
     "lpc_load_state": [_P, _P, _SZ],
+    "lpc_stream_copy": [_P, _P, _SZ, _P],
+    "lpc_describe": [_P, ctypes.c_char_p, _SZ],
 }
 
 

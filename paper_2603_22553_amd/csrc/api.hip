@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -63,8 +64,17 @@ struct Layout {
            off_staging = 0, off_scalars = 0;
     size_t off_rho[2] = {0, 0}, off_re[2] = {0, 0}, off_im[2] = {0, 0};
     size_t off_m1[2][3] = {}, off_m2[2][3] = {};
+    size_t partial_bytes = 0;
     size_t total = 0;
 };
+
+// Steps whose partial sums fit the partials buffer together (finalised in one launch).
+void set_chunk(Layout &L)
+{
+    const int64_t per_step = int64_t(L.K) * L.plan.nblocks * 8;
+    int64_t c = int64_t(L.partial_bytes) / per_step;
+    L.chunk = std::max<int64_t>(1, std::min<int64_t>(kChunkMax, c));
+}
 
 bool fid_of(const lpc_config &c)
 {
@@ -107,6 +117,9 @@ lpc_status validate_config(const lpc_config *c)
     return LPC_OK;
 }
 
+// Buffer placement for cfg. The sweep plan depends on the device (resident workgroups per
+// compute unit), so the per-step partial sums are sized for the largest plan; `plan` and
+// `chunk` are provisional here and fixed by lpc_create.
 Layout plan_layout(const lpc_config &c)
 {
     Layout L;
@@ -114,13 +127,8 @@ Layout plan_layout(const lpc_config &c)
     L.K = 3 * c.n_regions + 6;
     L.storage = c.precision == LPC_PREC_FP64 ? 8 : 4;
     lpc::Geometry g{c.n[0], c.n[1], c.n[2], {c.bc[0], c.bc[1], c.bc[2]}};
-    L.plan = lpc::make_plan(g, 0);
-    const int64_t per_step = int64_t(L.K) * L.plan.nblocks * 8;
-    L.chunk = kPartialBudget / per_step;
-    if (L.chunk > kChunkMax)
-        L.chunk = kChunkMax;
-    if (L.chunk < 1)
-        L.chunk = 1;
+    L.plan = lpc::make_plan(g, 1, 256);
+    const int64_t per_step_max = int64_t(L.K) * lpc::max_sweep_blocks(g) * 8;
     L.staging = L.n < kStagingMax ? L.n : kStagingMax;
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -141,14 +149,13 @@ Layout plan_layout(const lpc_config &c)
             L.off_m2[b][a] = take(msd_of(c) ? ns : 0);
         }
     }
-    size_t partial_bytes = size_t(per_step) * size_t(L.chunk);
-    if (partial_bytes < 4096 * 8)
-        partial_bytes = 4096 * 8;
-    L.off_partials = take(partial_bytes);
+    L.partial_bytes = size_t(std::max<int64_t>(kPartialBudget, per_step_max));
+    L.off_partials = take(L.partial_bytes);
     L.off_records = take(size_t(c.max_records) * L.K * 8);
     L.off_staging = take(size_t(L.staging) * 8);
     L.off_scalars = take(kScalars * 8);
     L.total = o;
+    set_chunk(L);
     return L;
 }
 
@@ -364,9 +371,18 @@ lpc_status lpc_create(const lpc_config *cfg, void *arena, size_t arena_bytes, vo
     lat->L = L;
     lat->stream = static_cast<hipStream_t>(stream);
     lat->arena = static_cast<char *>(arena);
-    if (hipGetDevice(&lat->device) != hipSuccess) {
+    int cus = 0;
+    if (hipGetDevice(&lat->device) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, lat->device) !=
+            hipSuccess) {
         delete lat;
-        return fail(LPC_ERR_DEVICE, "hipGetDevice failed");
+        return fail(LPC_ERR_DEVICE, "device query failed");
+    }
+    {
+        lpc::Geometry g{cfg->n[0], cfg->n[1], cfg->n[2], {cfg->bc[0], cfg->bc[1], cfg->bc[2]}};
+        const int occ = lpc::sweep_blocks_per_cu(cfg->precision, cfg->track, cfg->n_regions);
+        lat->L.plan = lpc::make_plan(g, occ, cus);
+        set_chunk(lat->L);
     }
     for (int b = 0; b < 2; ++b) {
         lpc::StateView &v = lat->st[b];
@@ -821,6 +837,33 @@ lpc_status lpc_load_state(lpc_lattice *lat, const void *buf, size_t len)
     LPC_HIP(hipMemcpy(lat->records(), p, size_t(h.rows) * lat->L.K * 8, hipMemcpyHostToDevice));
     lat->steps_done = h.steps_done;
     lat->initialized = true;
+    return ok();
+}
+
+lpc_status lpc_stream_copy(const void *src, void *dst, size_t bytes, void *stream)
+{
+    if (!src || !dst)
+        return fail(LPC_ERR_ARG, "NULL buffer");
+    if (bytes % 16 || reinterpret_cast<uintptr_t>(src) % 16 || reinterpret_cast<uintptr_t>(dst) % 16)
+        return fail(LPC_ERR_ARG, "buffers and size must be 16-byte aligned");
+    const char *a = static_cast<const char *>(src);
+    const char *b = static_cast<const char *>(dst);
+    if (a < b + bytes && b < a + bytes)
+        return fail(LPC_ERR_ARG, "buffers overlap");
+    LPC_HIP(lpc::launch_stream_copy(src, dst, int64_t(bytes / 16), static_cast<hipStream_t>(stream)));
+    return ok();
+}
+
+lpc_status lpc_describe(const lpc_lattice *lat, char *buf, size_t cap)
+{
+    if (!lat || !buf || cap == 0)
+        return fail(LPC_ERR_ARG, "NULL argument");
+    const lpc::SweepPlan &p = lat->L.plan;
+    snprintf(buf, cap,
+             "tile %dx%d, zc %d, grid %dx%dx%d = %lld workgroups, %lld steps per finalize, "
+             "arena %zu bytes",
+             p.tx, p.ty, p.zc, p.gx, p.gy, p.gz, (long long)p.nblocks, (long long)lat->L.chunk,
+             lat->L.total);
     return ok();
 }
 

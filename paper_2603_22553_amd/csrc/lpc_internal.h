@@ -45,7 +45,12 @@ struct StepArgs {
     double *partials;    // [K][nblocks] for this step
 };
 
-SweepPlan make_plan(const Geometry &g, int32_t kernel_hint);
+// Upper bound on the workgroups of any plan for g (sizes the per-step partial sums).
+int64_t max_sweep_blocks(const Geometry &g);
+// Plan for g given the resident sweep workgroups per compute unit and the compute units.
+SweepPlan make_plan(const Geometry &g, int32_t blocks_per_cu, int32_t cus);
+// Resident sweep workgroups per compute unit for this precision, track set and regions.
+int sweep_blocks_per_cu(int32_t precision, uint32_t track, int32_t R);
 
 hipError_t launch_step(const SweepPlan &plan, const StepArgs &a, hipStream_t s);
 hipError_t launch_record(const SweepPlan &plan, const StepArgs &a, hipStream_t s);
@@ -64,5 +69,8 @@ hipError_t launch_boltzmann_weights(int32_t precision, const void *F, double Fmi
 // rho_i = w_i * scale_num / (*Z) in place.
 hipError_t launch_boltzmann_scale(double *w, int64_t n, double numer, const double *Z,
                                   hipStream_t s);
+
+// Plain copy of n16 16-byte words (calibration kernel).
+hipError_t launch_stream_copy(const void *src, void *dst, int64_t n16, hipStream_t s);
 
 }  // namespace lpc

@@ -25,6 +25,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 namespace lpc {
 namespace {
 
@@ -51,25 +53,6 @@ __host__ __device__ inline View<S> typed(const StateView &v)
     return t;
 }
 
-// Hop probabilities of one link, Eq. (1): p_out = p(i->j), p_in = p(j->i).
-__device__ inline void link_probs(double Fi, double Fj, double p0, double &p_out, double &p_in)
-{
-    const double dF = Fj - Fi;
-    const double pe = p0 * exp(-fabs(dF));
-    const bool up = dF > 0.0;
-    p_out = up ? pe : p0;
-    p_in = up ? p0 : pe;
-}
-
-__device__ inline void link_probs(float Fi, float Fj, float p0, double &p_out, double &p_in)
-{
-    const float dF = Fj - Fi;
-    const float pe = p0 * expf(-fabsf(dF));
-    const bool up = dF > 0.0f;
-    p_out = static_cast<double>(up ? pe : p0);
-    p_in = static_cast<double>(up ? p0 : pe);
-}
-
 // Population flux of a link with both products rounded separately, so that the value
 // computed at site j is exactly the negation of the one computed at site i.
 __device__ inline double exact_flux(double p_in, double xj, double p_out, double xi)
@@ -78,32 +61,6 @@ __device__ inline double exact_flux(double p_in, double xj, double p_out, double
     const double a = p_in * xj;
     const double b = p_out * xi;
     return a - b;
-}
-
-// Neighbour index one hop along an axis (sign +1 / -1); false across a closed face.
-__device__ inline bool neighbour(int c, int n, int bc, int64_t stride, int sgn, int64_t i,
-                                 int64_t &j)
-{
-    if (sgn > 0) {
-        if (c + 1 < n) {
-            j = i + stride;
-            return true;
-        }
-        if (bc == 0) {
-            j = i - static_cast<int64_t>(n - 1) * stride;
-            return true;
-        }
-        return false;
-    }
-    if (c > 0) {
-        j = i - stride;
-        return true;
-    }
-    if (bc == 0) {
-        j = i + static_cast<int64_t>(n - 1) * stride;
-        return true;
-    }
-    return false;
 }
 
 // Register accumulators of one thread's record contributions.
@@ -193,96 +150,141 @@ __device__ inline int64_t logical_block(int64_t b, int64_t padded)
 
 // ---------------------------------------------------------------------------- one site
 
-template <typename S, bool FID, bool MSD, int MAXR>
-__device__ inline void step_site(const StepArgs &a, const View<S> &src, const View<S> &dst, int x,
-                                 int y, int z, RecAcc<MAXR> &acc)
+// Values of one site that its neighbours read: population, free energy, magnetisation
+// and displacement moments, in the storage type S (rho is always double).
+template <typename S, bool FID, bool MSD>
+struct Cell {
+    double rho;
+    S F;
+    S re, im;
+    S m1[3], m2[3];
+};
+
+template <typename S, bool FID, bool MSD>
+__device__ inline void load_cell(Cell<S, FID, MSD> &c, const View<S> &v, const S *F, int64_t i)
 {
-    const Geometry &g = a.g;
-    const S *F = static_cast<const S *>(a.F);
-    const S *TH = static_cast<const S *>(a.theta);
-    const int64_t sx = 1, sy = g.nx, sz = static_cast<int64_t>(g.nx) * g.ny;
-    const int64_t i = x + sy * y + sz * z;
-    const S Fi = F[i];
-    const S p0 = static_cast<S>(a.p0);
-    const double rho_i = src.rho[i];
-    double f_rho = 0.0;
-    double re_i = 0.0, im_i = 0.0, f_re = 0.0, f_im = 0.0;
+    c.rho = v.rho[i];
+    c.F = F[i];
     if (FID) {
-        re_i = static_cast<double>(src.re[i]);
-        im_i = static_cast<double>(src.im[i]);
+        c.re = v.re[i];
+        c.im = v.im[i];
     }
-    double m1_i[3] = {0.0, 0.0, 0.0}, m2_i[3] = {0.0, 0.0, 0.0};
-    double f1[3] = {0.0, 0.0, 0.0}, f2[3] = {0.0, 0.0, 0.0};
     if (MSD) {
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-            m1_i[b] = static_cast<double>(src.m1[b][i]);
-            m2_i[b] = static_cast<double>(src.m2[b][i]);
+            c.m1[b] = v.m1[b][i];
+            c.m2[b] = v.m2[b][i];
         }
     }
-    const int c[3] = {x, y, z};
-    const int n[3] = {g.nx, g.ny, g.nz};
-    const int64_t st[3] = {sx, sy, sz};
+}
+
+// Accumulated link fluxes of one site: rho in double, the rest in the arithmetic type.
+template <typename S>
+struct Flux {
+    double rho;
+    S re, im, m1[3], m2[3];
+};
+
+__device__ inline float fast_exp(float v)
+{
+    return __expf(v);
+}
+__device__ inline double fast_exp(double v)
+{
+    return exp(v);
+}
+
+// Hop probabilities of one link in the arithmetic type, Eq. (1): p_out = p(i->j),
+// p_in = p(j->i). The same (|dF|, direction) gives bit-identical values at both ends.
+template <typename S>
+__device__ inline void link_pair(S Fi, S Fj, S p0, S &p_out, S &p_in)
+{
+    const S dF = Fj - Fi;
+    const S pe = p0 * fast_exp(-(dF > S(0) ? dF : -dF));
+    const bool up = dF > S(0);
+    p_out = up ? pe : p0;
+    p_in = up ? p0 : pe;
+}
+
+// Adds the fluxes of the link to neighbour `nb`, which lies one hop along axis AX with
+// sign `sgn` (+1 / -1); the arriving move nb -> i has hop component d = -sgn.
+template <int AX, typename S, bool FID, bool MSD>
+__device__ inline void add_link(const Cell<S, FID, MSD> &c, const Cell<S, FID, MSD> &nb, int sgn,
+                                S p0, Flux<S> &f)
+{
+    S p_out, p_in;
+    link_pair(c.F, nb.F, p0, p_out, p_in);
+    f.rho += exact_flux(static_cast<double>(p_in), nb.rho, static_cast<double>(p_out), c.rho);
+    if (FID) {
+        f.re += p_in * nb.re - p_out * c.re;
+        f.im += p_in * nb.im - p_out * c.im;
+    }
+    if (MSD) {
+        const S d = static_cast<S>(-sgn);
+        const S rj = static_cast<S>(nb.rho);
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-#pragma unroll
-        for (int sg = 0; sg < 2; ++sg) {
-            const int sgn = sg == 0 ? 1 : -1;
-            int64_t j;
-            if (!neighbour(c[ax], n[ax], g.bc[ax], st[ax], sgn, i, j))
-                continue;  // attempt across a closed face: the particle stays
-            double p_out, p_in;
-            link_probs(Fi, F[j], p0, p_out, p_in);
-            const double rho_j = src.rho[j];
-            f_rho += exact_flux(p_in, rho_j, p_out, rho_i);
-            if (FID) {
-                f_re += p_in * static_cast<double>(src.re[j]) - p_out * re_i;
-                f_im += p_in * static_cast<double>(src.im[j]) - p_out * im_i;
-            }
-            if (MSD) {
-                const double d = -sgn;  // hop j -> i along ax (unwrapped)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) {
-                    const double m1j = static_cast<double>(src.m1[b][j]);
-                    const double m2j = static_cast<double>(src.m2[b][j]);
-                    if (b == ax) {
-                        f1[b] += p_in * (m1j + d * rho_j) - p_out * m1_i[b];
-                        f2[b] += p_in * (m2j + 2.0 * d * m1j + rho_j) - p_out * m2_i[b];
-                    } else {
-                        f1[b] += p_in * m1j - p_out * m1_i[b];
-                        f2[b] += p_in * m2j - p_out * m2_i[b];
-                    }
-                }
+        for (int b = 0; b < 3; ++b) {
+            if (b == AX) {
+                f.m1[b] += p_in * (nb.m1[b] + d * rj) - p_out * c.m1[b];
+                f.m2[b] += p_in * (nb.m2[b] + S(2) * d * nb.m1[b] + rj) - p_out * c.m2[b];
+            } else {
+                f.m1[b] += p_in * nb.m1[b] - p_out * c.m1[b];
+                f.m2[b] += p_in * nb.m2[b] - p_out * c.m2[b];
             }
         }
     }
-    const double rho_n = rho_i + f_rho;
-    dst.rho[i] = rho_n;
+}
+
+__device__ inline void half_angle(double t, double &s, double &c)
+{
+    sincos(0.5 * t, &s, &c);
+}
+__device__ inline void half_angle(float t, float &s, float &c)
+{
+    sincosf(0.5f * t, &s, &c);
+}
+
+// State arrays are written once per step and not read again within it: stream them past
+// the caches.
+template <typename T>
+__device__ inline void stream_store(T *p, T v)
+{
+    __builtin_nontemporal_store(v, p);
+}
+
+// New state of a site from its old values and link fluxes; stores it and adds its record
+// contributions.
+template <typename S, bool FID, bool MSD, int MAXR>
+__device__ inline void finish_site(const Cell<S, FID, MSD> &c, const Flux<S> &f, S theta, int r,
+                                   const View<S> &dst, int64_t i, RecAcc<MAXR> &acc)
+{
+    const double rho_n = c.rho + f.rho;
+    stream_store(dst.rho + i, rho_n);
     double out_re = 0.0, out_im = 0.0;
     if (FID) {
-        const double gre = re_i + f_re, gim = im_i + f_im;
-        double sh, ch;
-        sincos(0.5 * static_cast<double>(TH[i]), &sh, &ch);
-        const double sn = 2.0 * sh * ch, cm1 = -2.0 * sh * sh;
-        const S nre = static_cast<S>(gre + (gre * cm1 - gim * sn));
-        const S nim = static_cast<S>(gim + (gim * cm1 + gre * sn));
-        dst.re[i] = nre;
-        dst.im[i] = nim;
+        const S gre = c.re + f.re, gim = c.im + f.im;
+        S sh, ch;
+        half_angle(theta, sh, ch);
+        const S sn = S(2) * sh * ch, cm1 = S(-2) * sh * sh;   // sin t, cos t - 1
+        const S nre = gre + (gre * cm1 - gim * sn);
+        const S nim = gim + (gim * cm1 + gre * sn);
+        stream_store(dst.re + i, nre);
+        stream_store(dst.im + i, nim);
         out_re = static_cast<double>(nre);
         out_im = static_cast<double>(nim);
     }
     if (MSD) {
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-            const S v1 = static_cast<S>(m1_i[b] + f1[b]);
-            const S v2 = static_cast<S>(m2_i[b] + f2[b]);
-            dst.m1[b][i] = v1;
-            dst.m2[b][i] = v2;
+            const S v1 = c.m1[b] + f.m1[b];
+            const S v2 = c.m2[b] + f.m2[b];
+            stream_store(dst.m1[b] + i, v1);
+            stream_store(dst.m2[b] + i, v2);
             acc.s1[b] += static_cast<double>(v1);
             acc.s2[b] += static_cast<double>(v2);
         }
     }
-    acc.add_site(MAXR == 1 ? 0 : a.region[i], out_re, out_im, rho_n);
+    acc.add_site(r, out_re, out_im, rho_n);
 }
 
 template <typename S, bool FID, bool MSD, int MAXR>
@@ -304,43 +306,270 @@ __device__ inline void record_site(const StepArgs &a, const View<S> &v, int64_t 
     acc.add_site(MAXR == 1 ? 0 : a.region[i], re, im, v.rho[i]);
 }
 
-// ---------------------------------------------------------------------------- kernels
+// LDS image of one z-plane of a tile with a one-site halo in x and y, one array per field.
+template <typename S, bool FID, bool MSD, int NL>
+struct TileLds {
+    double rho[NL];
+    S F[NL];
+    S re[FID ? NL : 1], im[FID ? NL : 1];
+    S m1[3][MSD ? NL : 1], m2[3][MSD ? NL : 1];
 
-constexpr int kDirectTX = 64, kDirectTY = 4, kDirectThreads = kDirectTX * kDirectTY;
-
-// One thread per (x, y) of a 64 x 4 tile, marching the workgroup's run of z-planes;
-// neighbours are read straight from global memory (cache hits inside the tile).
-template <typename S, bool FID, bool MSD, int MAXR, bool RECORD_ONLY>
-__global__ __launch_bounds__(kDirectThreads) void k_sweep_direct(StepArgs a, SweepPlan p,
-                                                                 int64_t padded)
-{
-    __shared__ double lds[(kDirectThreads / kWave) * (3 * MAXR + 6)];
-    const int64_t blk = logical_block(blockIdx.x, padded);
-    if (blk >= p.nblocks)
-        return;
-    const int bx = static_cast<int>(blk % p.gx);
-    const int64_t rest = blk / p.gx;
-    const int by = static_cast<int>(rest % p.gy);
-    const int bz = static_cast<int>(rest / p.gy);
-    const int x = bx * kDirectTX + static_cast<int>(threadIdx.x % kDirectTX);
-    const int y = by * kDirectTY + static_cast<int>(threadIdx.x / kDirectTX);
-    const View<S> src = typed<S>(a.src);
-    const View<S> dst = typed<S>(a.dst);
-    RecAcc<MAXR> acc;
-    acc.zero();
-    if (x < a.g.nx && y < a.g.ny) {
-        const int z0 = bz * p.zc;
-        const int z1 = min(a.g.nz, z0 + p.zc);
-        for (int z = z0; z < z1; ++z) {
-            if (RECORD_ONLY) {
-                const int64_t i = x + static_cast<int64_t>(a.g.nx) * (y + static_cast<int64_t>(a.g.ny) * z);
-                record_site<S, FID, MSD, MAXR>(a, src, i, acc);
-            } else {
-                step_site<S, FID, MSD, MAXR>(a, src, dst, x, y, z, acc);
+    template <typename C>
+    __device__ void put(int s, const C &c)
+    {
+        rho[s] = c.rho;
+        F[s] = c.F;
+        if (FID) {
+            re[s] = c.re;
+            im[s] = c.im;
+        }
+        if (MSD) {
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                m1[b][s] = c.m1[b];
+                m2[b][s] = c.m2[b];
             }
         }
     }
-    block_reduce<MAXR, kDirectThreads / kWave>(acc, a.R, a.K, a.partials, p.nblocks, blk, lds);
+
+    template <typename C>
+    __device__ void get(int s, C &c) const
+    {
+        c.rho = rho[s];
+        c.F = F[s];
+        if (FID) {
+            c.re = re[s];
+            c.im = im[s];
+        }
+        if (MSD) {
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                c.m1[b] = m1[b][s];
+                c.m2[b] = m2[b][s];
+            }
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------- kernels
+
+constexpr int kTileX = 64;
+
+__device__ inline void tile_coords(const SweepPlan &p, int64_t blk, int &bx, int &by, int &bz)
+{
+    bx = static_cast<int>(blk % p.gx);
+    const int64_t rest = blk / p.gx;
+    by = static_cast<int>(rest % p.gy);
+    bz = static_cast<int>(rest / p.gy);
+}
+
+// Per-thread constants of one tile: the thread's column, its neighbours' existence and its
+// halo site.
+struct TileThread {
+    int64_t col, hcol;
+    int li, hslot;
+    bool act, has_xm, has_xp, has_ym, has_yp;
+};
+
+// One z-plane of the tile: stage it in LDS buffer `L` (own site + halo site), wait for the
+// whole tile, prefetch plane z+2 (own column) into `nx2` and the halo of plane z+1 into
+// `halo`, then update every site of the plane from LDS (x, y) and registers (z).
+template <typename S, bool FID, bool MSD, int MAXR, int TY, typename LDS>
+__device__ __forceinline__ void plane_step(LDS &L, const StepArgs &a, const TileThread &th,
+                                           const View<S> &src, const View<S> &dst, const S *F,
+                                           const S *TH, int64_t plane, int z, int z1,
+                                           const Cell<S, FID, MSD> &prv,
+                                           const Cell<S, FID, MSD> &cur,
+                                           const Cell<S, FID, MSD> &nxt,
+                                           Cell<S, FID, MSD> &nx2, Cell<S, FID, MSD> &halo,
+                                           RecAcc<MAXR> &acc)
+{
+    constexpr int COLS = kTileX + 2;
+    const Geometry &g = a.g;
+    const bool zper = g.bc[2] == 0;
+    if (th.act)
+        L.put(th.li, cur);
+    if (th.hslot >= 0)
+        L.put(th.hslot, halo);
+    __syncthreads();
+    if (z + 1 < z1) {
+        const int zn = z + 2 < g.nz ? z + 2 : (zper ? (z + 2) % g.nz : -1);
+        if (th.act && zn >= 0)
+            load_cell(nx2, src, F, th.col + plane * zn);
+        if (th.hslot >= 0)
+            load_cell(halo, src, F, th.hcol + plane * (z + 1));
+    }
+    if (!th.act)
+        return;
+    const S p0 = static_cast<S>(a.p0);
+    Flux<S> f{};
+    Cell<S, FID, MSD> nb;
+    if (th.has_xm) {
+        L.get(th.li - 1, nb);
+        add_link<0>(cur, nb, -1, p0, f);
+    }
+    if (th.has_xp) {
+        L.get(th.li + 1, nb);
+        add_link<0>(cur, nb, +1, p0, f);
+    }
+    if (th.has_ym) {
+        L.get(th.li - COLS, nb);
+        add_link<1>(cur, nb, -1, p0, f);
+    }
+    if (th.has_yp) {
+        L.get(th.li + COLS, nb);
+        add_link<1>(cur, nb, +1, p0, f);
+    }
+    if (z > 0 || zper)
+        add_link<2>(cur, prv, -1, p0, f);
+    if (z + 1 < g.nz || zper)
+        add_link<2>(cur, nxt, +1, p0, f);
+    const int64_t i = plane * z + th.col;
+    const S theta = FID ? TH[i] : S(0);
+    const int r = MAXR == 1 ? 0 : a.region[i];
+    finish_site<S, FID, MSD, MAXR>(cur, f, theta, r, dst, i, acc);
+}
+
+#ifndef LPC_MIN_WAVES
+#define LPC_MIN_WAVES 1
+#endif
+
+// One step over a 64 x TY tile of x-y columns and the workgroup's run of z-planes. Each
+// thread owns one column and keeps planes z-1, z, z+1 of it in registers, with plane z+2
+// in flight; the four register sets rotate roles from plane to plane, so no move forces
+// an early wait on a prefetch. The x and y neighbours of plane z come from an LDS image of
+// the plane with a one-site halo, double-buffered so that one barrier per plane suffices.
+// The halo sites (a row below and above the tile, a column left and right of it; wrapped
+// on periodic axes, absent across closed faces) are spread over threads, one site each,
+// and fetched one plane ahead.
+template <typename S, bool FID, bool MSD, int MAXR, int TY>
+__global__ __launch_bounds__(kTileX *TY, LPC_MIN_WAVES) void k_sweep_tile(StepArgs a, SweepPlan p,
+                                                                         int64_t padded)
+{
+    constexpr int TX = kTileX, COLS = TX + 2, NL = COLS * (TY + 2);
+    static_assert(TX * TY >= 2 * TX + 2 * TY, "one halo site per thread");
+    using C = Cell<S, FID, MSD>;
+    __shared__ TileLds<S, FID, MSD, NL> L0, L1;
+    __shared__ double red[TY * (3 * MAXR + 6)];
+    const int64_t blk = logical_block(blockIdx.x, padded);
+    if (blk >= p.nblocks)
+        return;
+    const Geometry &g = a.g;
+    int bx, by, bz;
+    tile_coords(p, blk, bx, by, bz);
+    const int t = static_cast<int>(threadIdx.x);
+    const int tx = t % TX, ty = t / TX;
+    const int x0 = bx * TX, y0 = by * TY;
+    const int x = x0 + tx, y = y0 + ty;
+    const int cols = min(TX, g.nx - x0), rows = min(TY, g.ny - y0);
+    const bool xper = g.bc[0] == 0, yper = g.bc[1] == 0, zper = g.bc[2] == 0;
+    TileThread th;
+    th.act = tx < cols && ty < rows;
+    th.has_xm = x > 0 || xper;
+    th.has_xp = x + 1 < g.nx || xper;
+    th.has_ym = y > 0 || yper;
+    th.has_yp = y + 1 < g.ny || yper;
+    th.col = x + static_cast<int64_t>(g.nx) * y;
+    th.li = (ty + 1) * COLS + tx + 1;
+    th.hslot = -1;
+    th.hcol = 0;
+    {
+        int hx = -1, hy = -1;
+        if (t < TX) {                                   // row below the tile
+            if (t < cols) {
+                hx = x0 + t;
+                hy = y0 > 0 ? y0 - 1 : (yper ? g.ny - 1 : -1);
+                th.hslot = t + 1;
+            }
+        } else if (t < 2 * TX) {                        // row above the tile
+            const int u = t - TX;
+            if (u < cols) {
+                hx = x0 + u;
+                hy = y0 + rows < g.ny ? y0 + rows : (yper ? (y0 + rows) % g.ny : -1);
+                th.hslot = (rows + 1) * COLS + u + 1;
+            }
+        } else if (t < 2 * TX + TY) {                   // column left of the tile
+            const int v = t - 2 * TX;
+            if (v < rows) {
+                hy = y0 + v;
+                hx = x0 > 0 ? x0 - 1 : (xper ? g.nx - 1 : -1);
+                th.hslot = (v + 1) * COLS;
+            }
+        } else if (t < 2 * TX + 2 * TY) {               // column right of the tile
+            const int v = t - 2 * TX - TY;
+            if (v < rows) {
+                hy = y0 + v;
+                hx = x0 + cols < g.nx ? x0 + cols : (xper ? (x0 + cols) % g.nx : -1);
+                th.hslot = (v + 1) * COLS + cols + 1;
+            }
+        }
+        if (hx < 0 || hy < 0)
+            th.hslot = -1;
+        else
+            th.hcol = hx + static_cast<int64_t>(g.nx) * hy;
+    }
+    const S *F = static_cast<const S *>(a.F);
+    const S *TH = static_cast<const S *>(a.theta);
+    const View<S> src = typed<S>(a.src);
+    const View<S> dst = typed<S>(a.dst);
+    const int64_t plane = static_cast<int64_t>(g.nx) * g.ny;
+    const int z0 = bz * p.zc, z1 = min(g.nz, z0 + p.zc);
+    C w0, w1, w2, w3, halo;
+    RecAcc<MAXR> acc;
+    acc.zero();
+    if (th.act) {
+        load_cell(w1, src, F, th.col + plane * z0);
+        const int zm = z0 > 0 ? z0 - 1 : (zper ? g.nz - 1 : -1);
+        const int zp = z0 + 1 < g.nz ? z0 + 1 : (zper ? (z0 + 1) % g.nz : -1);
+        if (zm >= 0)
+            load_cell(w0, src, F, th.col + plane * zm);
+        if (zp >= 0)
+            load_cell(w2, src, F, th.col + plane * zp);
+    }
+    if (th.hslot >= 0)
+        load_cell(halo, src, F, th.hcol + plane * z0);
+    // roles (prv, cur, nxt, in-flight) rotate through w0..w3 with period 4; LDS buffers
+    // alternate with period 2
+    for (int z = z0; z < z1; z += 4) {
+        plane_step<S, FID, MSD, MAXR, TY>(L0, a, th, src, dst, F, TH, plane, z, z1, w0, w1, w2, w3, halo, acc);
+        if (z + 1 >= z1)
+            break;
+        plane_step<S, FID, MSD, MAXR, TY>(L1, a, th, src, dst, F, TH, plane, z + 1, z1, w1, w2, w3, w0, halo, acc);
+        if (z + 2 >= z1)
+            break;
+        plane_step<S, FID, MSD, MAXR, TY>(L0, a, th, src, dst, F, TH, plane, z + 2, z1, w2, w3, w0, w1, halo, acc);
+        if (z + 3 >= z1)
+            break;
+        plane_step<S, FID, MSD, MAXR, TY>(L1, a, th, src, dst, F, TH, plane, z + 3, z1, w3, w0, w1, w2, halo, acc);
+    }
+    __syncthreads();
+    block_reduce<MAXR, TY>(acc, a.R, a.K, a.partials, p.nblocks, blk, red);
+}
+
+// Record contributions of the current state (no step), on the same tiles as the sweep.
+template <typename S, bool FID, bool MSD, int MAXR, int TY>
+__global__ __launch_bounds__(kTileX *TY) void k_record_tile(StepArgs a, SweepPlan p,
+                                                              int64_t padded)
+{
+    __shared__ double red[TY * (3 * MAXR + 6)];
+    const int64_t blk = logical_block(blockIdx.x, padded);
+    if (blk >= p.nblocks)
+        return;
+    int bx, by, bz;
+    tile_coords(p, blk, bx, by, bz);
+    const int x = bx * kTileX + static_cast<int>(threadIdx.x) % kTileX;
+    const int y = by * TY + static_cast<int>(threadIdx.x) / kTileX;
+    const View<S> src = typed<S>(a.src);
+    RecAcc<MAXR> acc;
+    acc.zero();
+    if (x < a.g.nx && y < a.g.ny) {
+        const int64_t plane = static_cast<int64_t>(a.g.nx) * a.g.ny;
+        const int64_t col = x + static_cast<int64_t>(a.g.nx) * y;
+        const int z1 = min(a.g.nz, (bz + 1) * p.zc);
+        for (int z = bz * p.zc; z < z1; ++z)
+            record_site<S, FID, MSD, MAXR>(a, src, col + plane * z, acc);
+    }
+    block_reduce<MAXR, TY>(acc, a.R, a.K, a.partials, p.nblocks, blk, red);
 }
 
 __global__ __launch_bounds__(256) void k_finalize(const double *partials, int64_t nblocks, int K,
@@ -417,6 +646,13 @@ __global__ void k_boltzmann_scale(double *w, int64_t n, double numer, const doub
         w[i] = numer * w[i] / z;
 }
 
+__global__ __launch_bounds__(256) void k_stream_copy(const float4 *__restrict__ src,
+                                                      float4 *__restrict__ dst, int64_t n)
+{
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += static_cast<int64_t>(gridDim.x) * 256)
+        dst[i] = src[i];
+}
+
 int grid_for(int64_t n, int threads)
 {
     int64_t g = (n + threads - 1) / threads;
@@ -427,84 +663,141 @@ int grid_for(int64_t n, int threads)
 
 // ---------------------------------------------------------------------------- dispatch
 
+#ifndef LPC_TILE_Y
+#define LPC_TILE_Y 4
+#endif
+constexpr int kTileY = LPC_TILE_Y;
+
 template <bool RECORD_ONLY>
-struct DirectLauncher {
+struct TileLauncher {
     template <typename S, bool FID, bool MSD, int MAXR>
     static hipError_t go(const SweepPlan &p, const StepArgs &a, hipStream_t s)
     {
         const int64_t padded = (p.nblocks + 7) / 8 * 8;
-        hipLaunchKernelGGL((k_sweep_direct<S, FID, MSD, MAXR, RECORD_ONLY>),
-                           dim3(static_cast<unsigned>(padded)), dim3(kDirectThreads), 0, s, a, p,
-                           padded);
+        if (RECORD_ONLY)
+            hipLaunchKernelGGL((k_record_tile<S, FID, MSD, MAXR, kTileY>),
+                               dim3(static_cast<unsigned>(padded)), dim3(kTileX * kTileY), 0, s,
+                               a, p, padded);
+        else
+            hipLaunchKernelGGL((k_sweep_tile<S, FID, MSD, MAXR, kTileY>),
+                               dim3(static_cast<unsigned>(padded)), dim3(kTileX * kTileY), 0, s,
+                               a, p, padded);
         return hipGetLastError();
     }
 };
 
-template <typename L, typename S, bool FID, bool MSD>
-hipError_t by_regions(const SweepPlan &p, const StepArgs &a, hipStream_t s)
+template <typename L, typename S, bool FID, bool MSD, typename... X>
+hipError_t by_regions(const SweepPlan &p, const StepArgs &a, hipStream_t s, X... x)
 {
     if (a.R == 1)
-        return L::template go<S, FID, MSD, 1>(p, a, s);
+        return L::template go<S, FID, MSD, 1>(p, a, s, x...);
     if (a.R == 2)
-        return L::template go<S, FID, MSD, 2>(p, a, s);
+        return L::template go<S, FID, MSD, 2>(p, a, s, x...);
     if (a.R <= 4)
-        return L::template go<S, FID, MSD, 4>(p, a, s);
-    return L::template go<S, FID, MSD, 8>(p, a, s);
+        return L::template go<S, FID, MSD, 4>(p, a, s, x...);
+    return L::template go<S, FID, MSD, 8>(p, a, s, x...);
 }
 
-template <typename L, typename S>
-hipError_t by_track(const SweepPlan &p, const StepArgs &a, hipStream_t s)
+template <typename L, typename S, typename... X>
+hipError_t by_track(const SweepPlan &p, const StepArgs &a, hipStream_t s, X... x)
 {
     const bool fid = a.track & 1u, msd = a.track & 2u;
     if (fid && msd)
-        return by_regions<L, S, true, true>(p, a, s);
+        return by_regions<L, S, true, true>(p, a, s, x...);
     if (fid)
-        return by_regions<L, S, true, false>(p, a, s);
+        return by_regions<L, S, true, false>(p, a, s, x...);
     if (msd)
-        return by_regions<L, S, false, true>(p, a, s);
-    return by_regions<L, S, false, false>(p, a, s);
+        return by_regions<L, S, false, true>(p, a, s, x...);
+    return by_regions<L, S, false, false>(p, a, s, x...);
 }
 
-template <typename L>
-hipError_t by_precision(const SweepPlan &p, const StepArgs &a, hipStream_t s)
+template <typename L, typename... X>
+hipError_t by_precision(const SweepPlan &p, const StepArgs &a, hipStream_t s, X... x)
 {
     if (a.precision == 0)
-        return by_track<L, double>(p, a, s);
-    return by_track<L, float>(p, a, s);
+        return by_track<L, double>(p, a, s, x...);
+    return by_track<L, float>(p, a, s, x...);
 }
 
 }  // namespace
 
-SweepPlan make_plan(const Geometry &g, int32_t kernel_hint)
+int64_t max_sweep_blocks(const Geometry &g)
 {
-    (void)kernel_hint;
+    const int64_t gx = (g.nx + kTileX - 1) / kTileX, gy = (g.ny + kTileY - 1) / kTileY;
+    const int64_t tiles = gx * gy;
+    int64_t gz = std::max<int64_t>((g.nz + 7) / 8, (8192 + tiles - 1) / tiles);
+    return tiles * std::min<int64_t>(g.nz, gz);
+}
+
+SweepPlan make_plan(const Geometry &g, int32_t blocks_per_cu, int32_t cus)
+{
     SweepPlan p{};
-    p.kernel = 0;
-    p.tx = kDirectTX;
-    p.ty = kDirectTY;
+    p.kernel = 1;
+    p.tx = kTileX;
+    p.ty = kTileY;
     p.gx = (g.nx + p.tx - 1) / p.tx;
     p.gy = (g.ny + p.ty - 1) / p.ty;
     const int64_t tiles = static_cast<int64_t>(p.gx) * p.gy;
-    const int64_t target = 4096;
-    int64_t gz = (target + tiles - 1) / tiles;
-    if (gz > g.nz)
-        gz = g.nz;
-    if (gz < 1)
-        gz = 1;
-    p.zc = static_cast<int32_t>((g.nz + gz - 1) / gz);
+    const int64_t conc = std::max(1, blocks_per_cu) * static_cast<int64_t>(std::max(1, cus));
+    const int64_t gz_max = max_sweep_blocks(g) / tiles;
+    // Pick the z-chunk: every resident slot busy until the end (greedy makespan of the
+    // chunks against the ideal), few extra planes per chunk (each chunk re-reads the two
+    // planes around it, mostly from cache), and a few rounds to absorb uneven progress.
+    double best = -1.0;
+    int32_t best_zc = g.nz;
+    for (int64_t gz = 1; gz <= gz_max; ++gz) {
+        const int32_t zc = static_cast<int32_t>((g.nz + gz - 1) / gz);
+        const int64_t gze = (g.nz + zc - 1) / zc;
+        if (gze != gz)
+            continue;
+        const int64_t T = tiles * gze;
+        const int64_t rounds = (T + conc - 1) / conc;
+        const double ideal = static_cast<double>(tiles) * g.nz / static_cast<double>(conc);
+        const double fill = ideal / static_cast<double>(rounds * zc);
+        const double pro = zc / (zc + 0.5);
+        const double eff = fill * pro * (1.0 - 0.05 / static_cast<double>(rounds));
+        if (eff > best + 1e-12) {
+            best = eff;
+            best_zc = zc;
+        }
+    }
+    p.zc = best_zc;
     p.gz = (g.nz + p.zc - 1) / p.zc;
     p.nblocks = tiles * p.gz;
     return p;
 }
 
+struct OccupancyQuery {
+    template <typename S, bool FID, bool MSD, int MAXR>
+    static hipError_t go(const SweepPlan &, const StepArgs &, hipStream_t, int *out)
+    {
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            out, reinterpret_cast<const void *>(&k_sweep_tile<S, FID, MSD, MAXR, kTileY>),
+            kTileX * kTileY, 0);
+    }
+};
+
+int sweep_blocks_per_cu(int32_t precision, uint32_t track, int32_t R)
+{
+    StepArgs a{};
+    a.precision = precision;
+    a.track = track;
+    a.R = R;
+    SweepPlan p{};
+    int n = 0;
+    if (by_precision<OccupancyQuery>(p, a, nullptr, &n) != hipSuccess || n < 1)
+        return 1;
+    return n;
+}
+
 hipError_t launch_step(const SweepPlan &plan, const StepArgs &a, hipStream_t s)
 {
-    return by_precision<DirectLauncher<false>>(plan, a, s);
+    return by_precision<TileLauncher<false>>(plan, a, s);
 }
 
 hipError_t launch_record(const SweepPlan &plan, const StepArgs &a, hipStream_t s)
 {
-    return by_precision<DirectLauncher<true>>(plan, a, s);
+    return by_precision<TileLauncher<true>>(plan, a, s);
 }
 
 hipError_t launch_finalize(const double *partials, int64_t nblocks, int32_t K, int64_t steps,
@@ -554,6 +847,13 @@ hipError_t launch_boltzmann_weights(int32_t precision, const void *F, double Fmi
     else
         hipLaunchKernelGGL(k_boltzmann_weights<float>, dim3(kWeightBlocks), dim3(256), 0, s,
                            static_cast<const float *>(F), Fmin, w, n, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_copy(const void *src, void *dst, int64_t n16, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_stream_copy, dim3(256 * 32), dim3(256), 0, s,
+                       static_cast<const float4 *>(src), static_cast<float4 *>(dst), n16);
     return hipGetLastError();
 }
 

@@ -105,6 +105,11 @@ class Lattice:
     def __exit__(self, *exc):
         self.close()
 
+    def describe(self) -> str:
+        buf = ctypes.create_string_buffer(512)
+        N.call("lpc_describe", self.handle, buf, len(buf))
+        return buf.value.decode()
+
     # -------------------------------------------------------------- inputs
     def _sites(self, a, dtype):
         a = np.ascontiguousarray(a, dtype=dtype).reshape(-1)

@@ -89,6 +89,10 @@ SMALL = [
     ((17, 13, 11), (PER, PER, PER), 2),     # ragged in x (< 64) and y (not a multiple of 4)
     ((70, 9, 5), (CLO, PER, CLO), 5),       # two x tiles, the second ragged
     ((5, 3, 33), (CLO, CLO, PER), 1),
+    ((64, 8, 37), (PER, PER, PER), 2),      # mid sizes: z-chunks of several planes
+    ((33, 12, 51), (PER, PER, CLO), 3),
+    ((130, 7, 23), (PER, CLO, PER), 2),
+    ((96, 40, 61), (PER, PER, PER), 1),
 ]
 
 
@@ -97,7 +101,7 @@ SMALL = [
 def test_small_lattices(oracle, shape, bc, R, precision):
     f = synth.random_fields(shape, seed=101 + sum(shape), F_scale=1.2, delta_scale=6.0,
                             n_regions=R)
-    steps = 300
+    steps = 300 if f.n_sites < 20000 else 60
     o = oracle.run(f.F, f.delta, f.region, R, steps, bc=bc)
     g = gpu_run(f, steps, bc=bc, precision=precision)
     compare(f"{shape} {bc} R={R} {precision}", g, o, R, precision)
