@@ -95,8 +95,8 @@ lpc_status validate_config(const lpc_config *c)
         if (c->bc[a] != LPC_BC_PERIODIC && c->bc[a] != LPC_BC_CLOSED)
             return fail(LPC_ERR_ARG, "bc[%d] = %d is not PERIODIC or CLOSED", a, c->bc[a]);
     }
-    if (int64_t(c->n[0]) * c->n[1] > (int64_t(1) << 31))
-        return fail(LPC_ERR_ARG, "nx * ny must not exceed 2^31");
+    if (int64_t(c->n[0]) * c->n[1] > (int64_t(1) << 28))
+        return fail(LPC_ERR_ARG, "nx * ny must not exceed 2^28 (one z-plane of doubles < 2 GiB)");
     if (c->precision != LPC_PREC_FP64 && c->precision != LPC_PREC_MIXED)
         return fail(LPC_ERR_ARG, "precision %d unknown", c->precision);
     if (c->track & ~uint32_t(LPC_TRACK_FID | LPC_TRACK_MSD))

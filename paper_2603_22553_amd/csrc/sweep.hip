@@ -4,15 +4,22 @@
 // propagation of section 2.2) for populations rho, complex magnetisation m and per-axis
 // displacement moments M1, M2, plus the per-step sums over sites of Eqs. (11)-(12).
 //
-// The update is written in flux form: for every link (i, j),
-//     x'_i += p(j->i) x_j - p(i->j) x_i,
-// which equals stay(i) x_i + sum_j p(j->i) x_j since stay(i) = 1 - sum_j p(i->j). The
-// flux of a link evaluated at its two ends is exactly antisymmetric in floating point,
-// so no per-site rounding of stay(i) can bias the totals from step to step: the total
-// population is conserved to rounding noise and the float-stored fields of the mixed
-// path do not drift. The one exponential of a link gives both directions:
-// p(i->j) = p0 e^{-|dF|} if F_j > F_i else p0, and p(j->i) the other way round (Eq. (1)).
-//
+// Per site i the step gathers from the six neighbours j with the hop probabilities of
+// Eq. (1) (one exponential per link gives both directions: p(i->j) = p0 e^{-|dF|} if
+// F_j > F_i else p0, and p(j->i) the other way round) and keeps the staying fraction
+// stay(i) = 1 - P_out(i), P_out(i) = sum_j p(i->j):
+//     x'_i = stay(i) x_i + sum_j p(j->i) x_j'        (x_j' with the hop's displacement)
+// Totals are only preserved step after step if stay(i) + P_out(i) is exactly one, so the
+// rounding of P_out must not repeat the same bias every step:
+//  - FP64 path: the population uses the flux form x'_i = x_i + sum_j [p(j->i) x_j -
+//    p(i->j) x_i], whose per-link terms are exactly antisymmetric between the two ends
+//    (both products rounded before the difference), so the total population is conserved
+//    to rounding noise. Magnetisation and moments use the stay form (a 1e-16 bias per
+//    step is far below any tolerance).
+//  - Mixed path (float storage and float hop probabilities): P_out is summed in double,
+//    where six floats add exactly, so stay(i) = 1 - P_out is exact and the update
+//    stay * x_i + sum is finished in double before the one rounding to float; every
+//    remaining rounding is unbiased.
 // Magnetisation rotates after the gather by the destination's phase (Eq. (13)), applied
 // as m + m (cos t - 1) + i m sin t with cos t - 1 = -2 sin^2(t/2), which keeps |m| from
 // drifting when t is stored in float.
@@ -51,6 +58,22 @@ __host__ __device__ inline View<S> typed(const StateView &v)
         t.m2[a] = static_cast<S *>(v.m2[a]);
     }
     return t;
+}
+
+// Element at a 32-bit byte offset from a workgroup-uniform base: the base lives in scalar
+// registers and the per-lane offset in one vector register.
+template <typename T>
+__device__ inline T ld(const T *base, uint32_t boff)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + boff);
+}
+
+// State arrays are written once per step and not read again within it: stream them past
+// the caches.
+template <typename T>
+__device__ inline void st(T *base, uint32_t boff, T v)
+{
+    __builtin_nontemporal_store(v, reinterpret_cast<T *>(reinterpret_cast<char *>(base) + boff));
 }
 
 // Population flux of a link with both products rounded separately, so that the value
@@ -160,28 +183,36 @@ struct Cell {
     S m1[3], m2[3];
 };
 
+// Byte offsets of one column (or halo column) in the 8-byte, S-sized and 1-byte arrays.
+struct Off {
+    uint32_t b8, bs, b1;
+};
+
+// Loads the values of a site that its neighbours read.
 template <typename S, bool FID, bool MSD>
-__device__ inline void load_cell(Cell<S, FID, MSD> &c, const View<S> &v, const S *F, int64_t i)
+__device__ inline void load_cell(Cell<S, FID, MSD> &c, const View<S> &v, const S *F, int64_t pz,
+                                 Off o)
 {
-    c.rho = v.rho[i];
-    c.F = F[i];
+    c.rho = ld(v.rho + pz, o.b8);
+    c.F = ld(F + pz, o.bs);
     if (FID) {
-        c.re = v.re[i];
-        c.im = v.im[i];
+        c.re = ld(v.re + pz, o.bs);
+        c.im = ld(v.im + pz, o.bs);
     }
     if (MSD) {
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-            c.m1[b] = v.m1[b][i];
-            c.m2[b] = v.m2[b][i];
+            c.m1[b] = ld(v.m1[b] + pz, o.bs);
+            c.m2[b] = ld(v.m2[b] + pz, o.bs);
         }
     }
 }
 
-// Accumulated link fluxes of one site: rho in double, the rest in the arithmetic type.
+// Gather accumulators of one site: sum_j p(j->i) x_j per field, the population term
+// (flux sum on the FP64 path, gather sum on the mixed path) and P_out in double.
 template <typename S>
-struct Flux {
-    double rho;
+struct Acc {
+    double rho, pout;
     S re, im, m1[3], m2[3];
 };
 
@@ -206,33 +237,74 @@ __device__ inline void link_pair(S Fi, S Fj, S p0, S &p_out, S &p_in)
     p_in = up ? p0 : pe;
 }
 
-// Adds the fluxes of the link to neighbour `nb`, which lies one hop along axis AX with
-// sign `sgn` (+1 / -1); the arriving move nb -> i has hop component d = -sgn.
-template <int AX, typename S, bool FID, bool MSD>
-__device__ inline void add_link(const Cell<S, FID, MSD> &c, const Cell<S, FID, MSD> &nb, int sgn,
-                                S p0, Flux<S> &f)
+// Gathers the fields arriving over one link from neighbour `nb`, which lies one hop along
+// axis AX with sign SGN; the arriving move nb -> i has hop component d = -SGN.
+template <int AX, int SGN, typename S, bool FID, bool MSD>
+__device__ inline void gather(const Cell<S, FID, MSD> &nb, S p_in, Acc<S> &f)
 {
-    S p_out, p_in;
-    link_pair(c.F, nb.F, p0, p_out, p_in);
-    f.rho += exact_flux(static_cast<double>(p_in), nb.rho, static_cast<double>(p_out), c.rho);
     if (FID) {
-        f.re += p_in * nb.re - p_out * c.re;
-        f.im += p_in * nb.im - p_out * c.im;
+        f.re = fma(p_in, nb.re, f.re);
+        f.im = fma(p_in, nb.im, f.im);
     }
     if (MSD) {
-        const S d = static_cast<S>(-sgn);
         const S rj = static_cast<S>(nb.rho);
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
             if (b == AX) {
-                f.m1[b] += p_in * (nb.m1[b] + d * rj) - p_out * c.m1[b];
-                f.m2[b] += p_in * (nb.m2[b] + S(2) * d * nb.m1[b] + rj) - p_out * c.m2[b];
+                // (X + d) and (X + d)^2 = X^2 + 2 d X + d^2 with d = -SGN = +-1
+                const S x1 = SGN > 0 ? nb.m1[b] - rj : nb.m1[b] + rj;
+                const S x2 = SGN > 0 ? fma(S(-2), nb.m1[b], nb.m2[b] + rj)
+                                     : fma(S(2), nb.m1[b], nb.m2[b] + rj);
+                f.m1[b] = fma(p_in, x1, f.m1[b]);
+                f.m2[b] = fma(p_in, x2, f.m2[b]);
             } else {
-                f.m1[b] += p_in * nb.m1[b] - p_out * c.m1[b];
-                f.m2[b] += p_in * nb.m2[b] - p_out * c.m2[b];
+                f.m1[b] = fma(p_in, nb.m1[b], f.m1[b]);
+                f.m2[b] = fma(p_in, nb.m2[b], f.m2[b]);
             }
         }
     }
+}
+
+template <int AX, int SGN, bool FID, bool MSD>
+__device__ inline void add_link(const Cell<double, FID, MSD> &c, const Cell<double, FID, MSD> &nb,
+                                double p0, Acc<double> &f)
+{
+    double p_out, p_in;
+    link_pair(c.F, nb.F, p0, p_out, p_in);
+    f.rho += exact_flux(p_in, nb.rho, p_out, c.rho);
+    f.pout += p_out;
+    gather<AX, SGN>(nb, p_in, f);
+}
+
+template <int AX, int SGN, bool FID, bool MSD>
+__device__ inline void add_link(const Cell<float, FID, MSD> &c, const Cell<float, FID, MSD> &nb,
+                                float p0, Acc<float> &f)
+{
+    float p_out, p_in;
+    link_pair(c.F, nb.F, p0, p_out, p_in);
+    f.rho = fma(static_cast<double>(p_in), nb.rho, f.rho);
+    f.pout += static_cast<double>(p_out);
+    gather<AX, SGN>(nb, p_in, f);
+}
+
+// stay * x + gathered, finished in double for float storage (one rounding to float).
+__device__ inline double stay_update(double stay, double x, double g)
+{
+    return fma(stay, x, g);
+}
+__device__ inline float stay_update(double stay, float x, float g)
+{
+    return static_cast<float>(fma(stay, static_cast<double>(x), static_cast<double>(g)));
+}
+
+__device__ inline double new_rho(double stay, double rho, const Acc<double> &f)
+{
+    (void)stay;
+    return rho + f.rho;
+}
+__device__ inline double new_rho(double stay, double rho, const Acc<float> &f)
+{
+    return fma(stay, rho, f.rho);
 }
 
 __device__ inline void half_angle(double t, double &s, double &c)
@@ -244,66 +316,40 @@ __device__ inline void half_angle(float t, float &s, float &c)
     sincosf(0.5f * t, &s, &c);
 }
 
-// State arrays are written once per step and not read again within it: stream them past
-// the caches.
-template <typename T>
-__device__ inline void stream_store(T *p, T v)
-{
-    __builtin_nontemporal_store(v, p);
-}
-
-// New state of a site from its old values and link fluxes; stores it and adds its record
+// New state of a site from its old values and gather sums; stores it and adds its record
 // contributions.
 template <typename S, bool FID, bool MSD, int MAXR>
-__device__ inline void finish_site(const Cell<S, FID, MSD> &c, const Flux<S> &f, S theta, int r,
-                                   const View<S> &dst, int64_t i, RecAcc<MAXR> &acc)
+__device__ inline void finish_site(const Cell<S, FID, MSD> &c, const Acc<S> &f, S theta, int r,
+                                   const View<S> &dst, int64_t pz, Off o, RecAcc<MAXR> &acc)
 {
-    const double rho_n = c.rho + f.rho;
-    stream_store(dst.rho + i, rho_n);
+    const double stay = 1.0 - f.pout;
+    const double rho_n = new_rho(stay, c.rho, f);
+    st(dst.rho + pz, o.b8, rho_n);
     double out_re = 0.0, out_im = 0.0;
     if (FID) {
-        const S gre = c.re + f.re, gim = c.im + f.im;
+        const S gre = stay_update(stay, c.re, f.re), gim = stay_update(stay, c.im, f.im);
         S sh, ch;
         half_angle(theta, sh, ch);
         const S sn = S(2) * sh * ch, cm1 = S(-2) * sh * sh;   // sin t, cos t - 1
         const S nre = gre + (gre * cm1 - gim * sn);
         const S nim = gim + (gim * cm1 + gre * sn);
-        stream_store(dst.re + i, nre);
-        stream_store(dst.im + i, nim);
+        st(dst.re + pz, o.bs, nre);
+        st(dst.im + pz, o.bs, nim);
         out_re = static_cast<double>(nre);
         out_im = static_cast<double>(nim);
     }
     if (MSD) {
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-            const S v1 = c.m1[b] + f.m1[b];
-            const S v2 = c.m2[b] + f.m2[b];
-            stream_store(dst.m1[b] + i, v1);
-            stream_store(dst.m2[b] + i, v2);
+            const S v1 = stay_update(stay, c.m1[b], f.m1[b]);
+            const S v2 = stay_update(stay, c.m2[b], f.m2[b]);
+            st(dst.m1[b] + pz, o.bs, v1);
+            st(dst.m2[b] + pz, o.bs, v2);
             acc.s1[b] += static_cast<double>(v1);
             acc.s2[b] += static_cast<double>(v2);
         }
     }
     acc.add_site(r, out_re, out_im, rho_n);
-}
-
-template <typename S, bool FID, bool MSD, int MAXR>
-__device__ inline void record_site(const StepArgs &a, const View<S> &v, int64_t i,
-                                   RecAcc<MAXR> &acc)
-{
-    double re = 0.0, im = 0.0;
-    if (FID) {
-        re = static_cast<double>(v.re[i]);
-        im = static_cast<double>(v.im[i]);
-    }
-    if (MSD) {
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            acc.s1[b] += static_cast<double>(v.m1[b][i]);
-            acc.s2[b] += static_cast<double>(v.m2[b][i]);
-        }
-    }
-    acc.add_site(MAXR == 1 ? 0 : a.region[i], re, im, v.rho[i]);
 }
 
 // LDS image of one z-plane of a tile with a one-site halo in x and y, one array per field.
@@ -355,6 +401,11 @@ struct TileLds {
 
 constexpr int kTileX = 64;
 
+#ifndef LPC_TILE_Y
+#define LPC_TILE_Y 4
+#endif
+constexpr int kTileY = LPC_TILE_Y;
+
 __device__ inline void tile_coords(const SweepPlan &p, int64_t blk, int &bx, int &by, int &bz)
 {
     bx = static_cast<int>(blk % p.gx);
@@ -366,7 +417,7 @@ __device__ inline void tile_coords(const SweepPlan &p, int64_t blk, int &bx, int
 // Per-thread constants of one tile: the thread's column, its neighbours' existence and its
 // halo site.
 struct TileThread {
-    int64_t col, hcol;
+    Off own, halo;
     int li, hslot;
     bool act, has_xm, has_xp, has_ym, has_yp;
 };
@@ -392,42 +443,51 @@ __device__ __forceinline__ void plane_step(LDS &L, const StepArgs &a, const Tile
     if (th.hslot >= 0)
         L.put(th.hslot, halo);
     __syncthreads();
+    // The column offsets are re-materialised every plane so that base + offset is not
+    // hoisted into per-array 64-bit vector registers: each load then takes the plane's
+    // scalar base plus one 32-bit vector offset.
+    // The column offsets are re-materialised every plane so that base + offset is not
+    // hoisted into per-array 64-bit vector registers: each load then takes the plane's
+    // scalar base plus one 32-bit vector offset.
+    Off own = th.own, hal = th.halo;
+    asm volatile("" : "+v"(own.b8), "+v"(own.bs), "+v"(own.b1), "+v"(hal.b8), "+v"(hal.bs));
     if (z + 1 < z1) {
-        const int zn = z + 2 < g.nz ? z + 2 : (zper ? (z + 2) % g.nz : -1);
+        // z + 2 <= nz here, so a periodic wrap lands on plane 0
+        const int zn = z + 2 < g.nz ? z + 2 : (zper ? 0 : -1);
         if (th.act && zn >= 0)
-            load_cell(nx2, src, F, th.col + plane * zn);
+            load_cell(nx2, src, F, plane * zn, own);
         if (th.hslot >= 0)
-            load_cell(halo, src, F, th.hcol + plane * (z + 1));
+            load_cell(halo, src, F, plane * (z + 1), hal);
     }
     if (!th.act)
         return;
     const S p0 = static_cast<S>(a.p0);
-    Flux<S> f{};
+    Acc<S> f{};
     Cell<S, FID, MSD> nb;
     if (th.has_xm) {
         L.get(th.li - 1, nb);
-        add_link<0>(cur, nb, -1, p0, f);
+        add_link<0, -1>(cur, nb, p0, f);
     }
     if (th.has_xp) {
         L.get(th.li + 1, nb);
-        add_link<0>(cur, nb, +1, p0, f);
+        add_link<0, +1>(cur, nb, p0, f);
     }
     if (th.has_ym) {
         L.get(th.li - COLS, nb);
-        add_link<1>(cur, nb, -1, p0, f);
+        add_link<1, -1>(cur, nb, p0, f);
     }
     if (th.has_yp) {
         L.get(th.li + COLS, nb);
-        add_link<1>(cur, nb, +1, p0, f);
+        add_link<1, +1>(cur, nb, p0, f);
     }
     if (z > 0 || zper)
-        add_link<2>(cur, prv, -1, p0, f);
+        add_link<2, -1>(cur, prv, p0, f);
     if (z + 1 < g.nz || zper)
-        add_link<2>(cur, nxt, +1, p0, f);
-    const int64_t i = plane * z + th.col;
-    const S theta = FID ? TH[i] : S(0);
-    const int r = MAXR == 1 ? 0 : a.region[i];
-    finish_site<S, FID, MSD, MAXR>(cur, f, theta, r, dst, i, acc);
+        add_link<2, +1>(cur, nxt, p0, f);
+    const int64_t pz = plane * z;
+    const S theta = FID ? ld(TH + pz, own.bs) : S(0);
+    const int r = MAXR == 1 ? 0 : ld(a.region + pz, own.b1);
+    finish_site<S, FID, MSD, MAXR>(cur, f, theta, r, dst, pz, own, acc);
 }
 
 #ifndef LPC_MIN_WAVES
@@ -441,7 +501,8 @@ __device__ __forceinline__ void plane_step(LDS &L, const StepArgs &a, const Tile
 // the plane with a one-site halo, double-buffered so that one barrier per plane suffices.
 // The halo sites (a row below and above the tile, a column left and right of it; wrapped
 // on periodic axes, absent across closed faces) are spread over threads, one site each,
-// and fetched one plane ahead.
+// and fetched one plane ahead. Plane offsets are workgroup-uniform; each thread keeps only
+// the 32-bit byte offsets of its column.
 template <typename S, bool FID, bool MSD, int MAXR, int TY>
 __global__ __launch_bounds__(kTileX *TY, LPC_MIN_WAVES) void k_sweep_tile(StepArgs a, SweepPlan p,
                                                                          int64_t padded)
@@ -469,10 +530,10 @@ __global__ __launch_bounds__(kTileX *TY, LPC_MIN_WAVES) void k_sweep_tile(StepAr
     th.has_xp = x + 1 < g.nx || xper;
     th.has_ym = y > 0 || yper;
     th.has_yp = y + 1 < g.ny || yper;
-    th.col = x + static_cast<int64_t>(g.nx) * y;
+    const uint32_t col = th.act ? static_cast<uint32_t>(x + g.nx * y) : 0u;
+    th.own = {col * 8u, col * static_cast<uint32_t>(sizeof(S)), col};
     th.li = (ty + 1) * COLS + tx + 1;
     th.hslot = -1;
-    th.hcol = 0;
     {
         int hx = -1, hy = -1;
         if (t < TX) {                                   // row below the tile
@@ -505,8 +566,8 @@ __global__ __launch_bounds__(kTileX *TY, LPC_MIN_WAVES) void k_sweep_tile(StepAr
         }
         if (hx < 0 || hy < 0)
             th.hslot = -1;
-        else
-            th.hcol = hx + static_cast<int64_t>(g.nx) * hy;
+        const uint32_t hcol = th.hslot >= 0 ? static_cast<uint32_t>(hx + g.nx * hy) : 0u;
+        th.halo = {hcol * 8u, hcol * static_cast<uint32_t>(sizeof(S)), hcol};
     }
     const S *F = static_cast<const S *>(a.F);
     const S *TH = static_cast<const S *>(a.theta);
@@ -518,16 +579,16 @@ __global__ __launch_bounds__(kTileX *TY, LPC_MIN_WAVES) void k_sweep_tile(StepAr
     RecAcc<MAXR> acc;
     acc.zero();
     if (th.act) {
-        load_cell(w1, src, F, th.col + plane * z0);
+        load_cell(w1, src, F, plane * z0, th.own);
         const int zm = z0 > 0 ? z0 - 1 : (zper ? g.nz - 1 : -1);
         const int zp = z0 + 1 < g.nz ? z0 + 1 : (zper ? (z0 + 1) % g.nz : -1);
         if (zm >= 0)
-            load_cell(w0, src, F, th.col + plane * zm);
+            load_cell(w0, src, F, plane * zm, th.own);
         if (zp >= 0)
-            load_cell(w2, src, F, th.col + plane * zp);
+            load_cell(w2, src, F, plane * zp, th.own);
     }
     if (th.hslot >= 0)
-        load_cell(halo, src, F, th.hcol + plane * z0);
+        load_cell(halo, src, F, plane * z0, th.halo);
     // roles (prv, cur, nxt, in-flight) rotate through w0..w3 with period 4; LDS buffers
     // alternate with period 2
     for (int z = z0; z < z1; z += 4) {
@@ -544,6 +605,25 @@ __global__ __launch_bounds__(kTileX *TY, LPC_MIN_WAVES) void k_sweep_tile(StepAr
     }
     __syncthreads();
     block_reduce<MAXR, TY>(acc, a.R, a.K, a.partials, p.nblocks, blk, red);
+}
+
+template <typename S, bool FID, bool MSD, int MAXR>
+__device__ inline void record_site(const StepArgs &a, const View<S> &v, int64_t i,
+                                   RecAcc<MAXR> &acc)
+{
+    double re = 0.0, im = 0.0;
+    if (FID) {
+        re = static_cast<double>(v.re[i]);
+        im = static_cast<double>(v.im[i]);
+    }
+    if (MSD) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            acc.s1[b] += static_cast<double>(v.m1[b][i]);
+            acc.s2[b] += static_cast<double>(v.m2[b][i]);
+        }
+    }
+    acc.add_site(MAXR == 1 ? 0 : a.region[i], re, im, v.rho[i]);
 }
 
 // Record contributions of the current state (no step), on the same tiles as the sweep.
@@ -662,11 +742,6 @@ int grid_for(int64_t n, int threads)
 }
 
 // ---------------------------------------------------------------------------- dispatch
-
-#ifndef LPC_TILE_Y
-#define LPC_TILE_Y 4
-#endif
-constexpr int kTileY = LPC_TILE_Y;
 
 template <bool RECORD_ONLY>
 struct TileLauncher {
