@@ -144,11 +144,63 @@ lpc_status lpc_read_uptake(lpc_lattice *lat, double *per_step_per_region, int64_
                            int64_t *len);
 lpc_status lpc_check(lpc_lattice *lat);
 
+/* Post-processing on the device. */
+
+/* Default FFT length of lpc_spectrum: the smallest power of two >= 8 (N + 1), N the steps
+ * done. The largest length the arena holds is the smallest power of two >= 8 max_records. */
+lpc_status lpc_spectrum_length(const lpc_lattice *lat, int64_t *n_fft);
+
+/* NMR spectrum, Eq. (9): the FID of `region` (-1: all regions) divided by its first sample,
+ * zero-filled to n_fft points (a power of two >= N + 1 and <= the largest length; 0 selects
+ * the default) and transformed with exp(-2 pi i k n / n_fft), so that a magnetisation
+ * precessing by +theta per step peaks at f = theta / (2 pi dt). Writes n_fft values in
+ * ascending frequency: ppm[j] = 1e6 f_j / larmor_hz with f_j = (j - n_fft/2) / (n_fft dt_s),
+ * and the real and imaginary parts. LPC_ERR_STATE if the FID is not tracked or starts at
+ * zero. */
+lpc_status lpc_spectrum(lpc_lattice *lat, int32_t region, int64_t n_fft, double *ppm, double *re,
+                        double *im, int64_t cap);
+
+/* Position in ppm of the maximum of Re F of the default-length spectrum, refined by the
+ * vertex of the parabola through the highest bin and its two neighbours. */
+lpc_status lpc_spectrum_peak(lpc_lattice *lat, int32_t region, double *peak_ppm);
+
+/* Diffusion coefficient per axis from the slope of the mean-square displacement between
+ * steps N/2 and N (the long-time form of Eqs. (6)-(7)): D_a = a^2 (MSD_a(N) - MSD_a(N/2)) /
+ * (2 (N - N/2) dt_s) in m^2/s, and ratio_a = D_a / D_bulk with D_bulk = p_hop a^2 / dt_s, the
+ * free-lattice value. Needs LPC_TRACK_MSD and N >= 2; 3 values each. */
+lpc_status lpc_diffusion(lpc_lattice *lat, double *D_m2_s, double *ratio);
+
+/* Populations of the current state summed over the planes perpendicular to `axis`
+ * (0 x, 1 y, 2 z): n[axis] values (the uptake profile across a film along x). */
+lpc_status lpc_uptake_profile(lpc_lattice *lat, int32_t axis, double *profile, int64_t cap);
+
 /* Checkpoint: the state arrays, step counter and records, into / from host memory.
  * With buf == NULL, save reports the size needed in *len. Load requires a lattice of
  * the same configuration; fields are not part of the checkpoint. */
 lpc_status lpc_save_state(lpc_lattice *lat, void *buf, size_t cap, size_t *len);
 lpc_status lpc_load_state(lpc_lattice *lat, const void *buf, size_t len);
+
+/* Batches: many lattices stepped together (independent particles of different sizes).
+ * Every step is one launch per tile width covering the tiles of all lattices that still
+ * have steps left; each lattice keeps its own tiles and reduction order, so its state and
+ * records end bit for bit as if it had been run alone with lpc_run. */
+
+/* Device bytes the work tables of a batch of `count` lattices need. */
+lpc_status lpc_batch_query_footprint(int32_t count, size_t *bytes);
+
+/* Groups `count` lattices (same device, precision and track set; any sizes, boundaries
+ * and region counts) in the caller's arena (>= footprint bytes, 256-byte aligned). The
+ * batch borrows the lattices: they must stay alive, and must not be stepped on their own,
+ * while the batch is in use. Work goes to `stream` (hipStream_t as void*). */
+lpc_status lpc_batch_create(lpc_lattice *const *lats, int32_t count, void *arena, size_t bytes,
+                            void *stream, lpc_batch **out);
+lpc_status lpc_batch_destroy(lpc_batch *batch);
+
+/* Advances lattice l by n_steps[l] >= 0 steps (count values). All lattices must be
+ * initialised and have record room for their steps (LPC_ERR_STATE otherwise; nothing is
+ * queued then). Synchronizes the stream each time the set of lattices still stepping
+ * changes (to rewrite the work tables); otherwise asynchronous. */
+lpc_status lpc_batch_run(lpc_batch *batch, const int64_t *n_steps);
 
 /* Calibration utility: copies `bytes` bytes from device buffer src to device buffer dst
  * (16-byte aligned, non-overlapping) with a plain streaming kernel on `stream`, so that

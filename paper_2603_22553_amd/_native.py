@@ -80,6 +80,15 @@ SIGNATURES = {
     "lpc_load_state": [_P, _P, _SZ],
     "lpc_stream_copy": [_P, _P, _SZ, _P],
     "lpc_describe": [_P, ctypes.c_char_p, _SZ],
+    "lpc_spectrum_length": [_P, _PI64],
+    "lpc_spectrum": [_P, _I32, _I64, _P, _P, _P, _I64],
+    "lpc_spectrum_peak": [_P, _I32, ctypes.POINTER(ctypes.c_double)],
+    "lpc_diffusion": [_P, _P, _P],
+    "lpc_uptake_profile": [_P, _I32, _P, _I64],
+    "lpc_batch_query_footprint": [_I32, _PSZ],
+    "lpc_batch_create": [_P, _I32, _P, _SZ, _P, ctypes.POINTER(_P)],
+    "lpc_batch_destroy": [_P],
+    "lpc_batch_run": [_P, _P],
 }
 
 

@@ -10,7 +10,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblpc.so")
-SOURCES = ["api.hip", "sweep.hip"]
+SOURCES = ["api.hip", "sweep.hip", "analysis.hip"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",

@@ -1,0 +1,222 @@
+// Post-processing kernels for gfx950: the NMR spectrum of a recorded FID (Eq. (9) of the
+// LPC3D paper), its peak, and population profiles of the state.
+//
+// The spectrum is a zero-filled radix-2 Stockham FFT in FP64 (out of place, ping-pong
+// between two device buffers, one launch per pass, twiddles from sincospi), with the
+// forward kernel exp(-2 pi i k n / L): a site precessing as exp(+i theta n) then peaks at
+// f = +theta / (2 pi dt). Reductions are deterministic (fixed-order tree per workgroup,
+// then a fixed-order pass over workgroups).
+#include "lpc_internal.h"
+
+#include <hip/hip_runtime.h>
+
+namespace lpc {
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ inline double warp_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// g[t] = G(t) / G(0) for t < rows (G summed over `region`, or over all regions if < 0),
+// zero for rows <= t < L.
+__global__ __launch_bounds__(kThreads) void k_fid_series(const double *rec, int64_t rows, int K,
+                                                         int R, int region, int64_t L, double2 *g)
+{
+    double c = 0.0, d = 0.0;
+    for (int r = 0; r < R; ++r) {
+        if (region >= 0 && r != region)
+            continue;
+        c += rec[2 * r];
+        d += rec[2 * r + 1];
+    }
+    const double den = c * c + d * d;
+    for (int64_t t = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; t < L;
+         t += static_cast<int64_t>(gridDim.x) * kThreads) {
+        double2 out = {0.0, 0.0};
+        if (t < rows) {
+            double a = 0.0, b = 0.0;
+            const double *row = rec + t * K;
+            for (int r = 0; r < R; ++r) {
+                if (region >= 0 && r != region)
+                    continue;
+                a += row[2 * r];
+                b += row[2 * r + 1];
+            }
+            out.x = (a * c + b * d) / den;
+            out.y = (b * c - a * d) / den;
+        }
+        g[t] = out;
+    }
+}
+
+// One radix-2 Stockham pass: sub-transforms of length p are merged into length 2p.
+__global__ __launch_bounds__(kThreads) void k_fft_pass(const double2 *__restrict__ x,
+                                                       double2 *__restrict__ y, int64_t n,
+                                                       int64_t p)
+{
+    const int64_t half = n / 2;
+    for (int64_t j = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; j < half;
+         j += static_cast<int64_t>(gridDim.x) * kThreads) {
+        const int64_t k = j & (p - 1);
+        double s, c;
+        sincospi(-static_cast<double>(k) / static_cast<double>(p), &s, &c);
+        const double2 a = x[j], b = x[j + half];
+        const double2 bw = {b.x * c - b.y * s, b.x * s + b.y * c};
+        y[2 * j - k] = {a.x + bw.x, a.y + bw.y};
+        y[2 * j - k + p] = {a.x - bw.x, a.y - bw.y};
+    }
+}
+
+// Ascending-frequency order: output j holds FFT bin (j + L/2) mod L; real parts in
+// out[0, L), imaginary parts in out[L, 2L).
+__global__ __launch_bounds__(kThreads) void k_spectrum_sorted(const double2 *X, int64_t L,
+                                                              double *out)
+{
+    for (int64_t j = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; j < L;
+         j += static_cast<int64_t>(gridDim.x) * kThreads) {
+        const double2 v = X[(j + L / 2) & (L - 1)];
+        out[j] = v.x;
+        out[L + j] = v.y;
+    }
+}
+
+// Largest value and its smallest index over v[0, n): per-workgroup candidates.
+__global__ __launch_bounds__(kThreads) void k_argmax_partial(const double *v, int64_t n,
+                                                             double *pval, int64_t *pidx)
+{
+    __shared__ double sv[kThreads];
+    __shared__ int64_t si[kThreads];
+    double best = -INFINITY;
+    int64_t bi = -1;
+    for (int64_t j = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; j < n;
+         j += static_cast<int64_t>(gridDim.x) * kThreads) {
+        if (v[j] > best) {
+            best = v[j];
+            bi = j;
+        }
+    }
+    sv[threadIdx.x] = best;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            const double ov = sv[threadIdx.x + s];
+            const int64_t oi = si[threadIdx.x + s];
+            if (ov > sv[threadIdx.x] || (ov == sv[threadIdx.x] && oi >= 0 &&
+                                         (si[threadIdx.x] < 0 || oi < si[threadIdx.x]))) {
+                sv[threadIdx.x] = ov;
+                si[threadIdx.x] = oi;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        pval[blockIdx.x] = sv[0];
+        pidx[blockIdx.x] = si[0];
+    }
+}
+
+__global__ void k_argmax_final(const double *pval, const int64_t *pidx, int nparts,
+                               int64_t *out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0)
+        return;
+    double best = -INFINITY;
+    int64_t bi = -1;
+    for (int b = 0; b < nparts; ++b) {
+        if (pidx[b] < 0)
+            continue;
+        if (pval[b] > best || (pval[b] == best && pidx[b] < bi)) {
+            best = pval[b];
+            bi = pidx[b];
+        }
+    }
+    *out = bi;
+}
+
+// profile[c] = sum of rho over the plane at coordinate c along `axis`; one workgroup per
+// plane, fixed summation order.
+__global__ __launch_bounds__(kThreads) void k_profile(const double *rho, int nx, int ny, int nz,
+                                                      int axis, double *profile)
+{
+    __shared__ double w[kThreads / 64];
+    const int c = blockIdx.x;
+    const int64_t n0 = axis == 0 ? ny : nx;           // first remaining axis (fastest)
+    const int64_t n1 = axis == 2 ? ny : nz;           // second remaining axis
+    const int64_t m = n0 * n1;
+    double acc = 0.0;
+    for (int64_t q = threadIdx.x; q < m; q += kThreads) {
+        const int64_t u = q % n0, v = q / n0;
+        int64_t x, y, z;
+        if (axis == 0) {
+            x = c; y = u; z = v;
+        } else if (axis == 1) {
+            x = u; y = c; z = v;
+        } else {
+            x = u; y = v; z = c;
+        }
+        acc += rho[x + static_cast<int64_t>(nx) * (y + static_cast<int64_t>(ny) * z)];
+    }
+    acc = warp_sum(acc);
+    if (threadIdx.x % 64 == 0)
+        w[threadIdx.x / 64] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < kThreads / 64; ++k)
+            t += w[k];
+        profile[c] = t;
+    }
+}
+
+int grid_for(int64_t n)
+{
+    int64_t g = (n + kThreads - 1) / kThreads;
+    return static_cast<int>(g < 1 ? 1 : (g > 4096 ? 4096 : g));
+}
+
+}  // namespace
+
+hipError_t launch_fid_spectrum(const double *records, int64_t rows, int32_t K, int32_t R,
+                               int32_t region, int64_t L, double2 *buf_a, double2 *buf_b,
+                               double *sorted_out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fid_series, dim3(grid_for(L)), dim3(kThreads), 0, s, records, rows, K, R,
+                       region, L, buf_a);
+    double2 *x = buf_a, *y = buf_b;
+    for (int64_t p = 1; p < L; p *= 2) {
+        hipLaunchKernelGGL(k_fft_pass, dim3(grid_for(L / 2)), dim3(kThreads), 0, s, x, y, L, p);
+        double2 *t = x;
+        x = y;
+        y = t;
+    }
+    // x holds the transform; the other buffer receives the sorted real / imaginary parts
+    double *out = sorted_out ? sorted_out : reinterpret_cast<double *>(y);
+    hipLaunchKernelGGL(k_spectrum_sorted, dim3(grid_for(L)), dim3(kThreads), 0, s, x, L, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_argmax(const double *v, int64_t n, double *pval, int64_t *pidx, int32_t nparts,
+                         int64_t *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_argmax_partial, dim3(nparts), dim3(kThreads), 0, s, v, n, pval, pidx);
+    hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(64), 0, s, pval, pidx, nparts, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_profile(const double *rho, const Geometry &g, int32_t axis, double *profile,
+                          hipStream_t s)
+{
+    const int n = axis == 0 ? g.nx : (axis == 1 ? g.ny : g.nz);
+    hipLaunchKernelGGL(k_profile, dim3(n), dim3(kThreads), 0, s, rho, g.nx, g.ny, g.nz, axis,
+                       profile);
+    return hipGetLastError();
+}
+
+}  // namespace lpc

@@ -47,6 +47,16 @@ constexpr int64_t kStagingMax = int64_t(1) << 22;   // doubles per host<->device
 constexpr int64_t kPartialBudget = int64_t(32) << 20; // bytes of per-step partials per chunk
 constexpr int64_t kChunkMax = 256;                    // steps finalised together
 constexpr int kScalars = 64;
+constexpr int kArgmaxParts = 256;
+
+// Smallest power of two >= 8 * samples: the default zero-filled FFT length.
+int64_t fft_length(int64_t samples)
+{
+    int64_t L = 1;
+    while (L < 8 * samples)
+        L *= 2;
+    return L;
+}
 
 size_t align_up(size_t v)
 {
@@ -61,7 +71,9 @@ struct Layout {
     int64_t chunk = 1;
     int64_t staging = 0;
     size_t off_F = 0, off_theta = 0, off_region = 0, off_partials = 0, off_records = 0,
-           off_staging = 0, off_scalars = 0;
+           off_staging = 0, off_scalars = 0, off_fft = 0, off_argmax = 0, off_profile = 0,
+           off_list = 0;
+    int64_t fft_max = 0;
     size_t off_rho[2] = {0, 0}, off_re[2] = {0, 0}, off_im[2] = {0, 0};
     size_t off_m1[2][3] = {}, off_m2[2][3] = {};
     size_t partial_bytes = 0;
@@ -117,6 +129,15 @@ lpc_status validate_config(const lpc_config *c)
     return LPC_OK;
 }
 
+// The one-entry work list through which lpc_run steps a lattice alone (the same kernels
+// step it inside a batch).
+struct SoloTables {
+    lpc::SweepItem item;
+    int64_t prefix[2];
+    lpc::FinalizeItem fin;
+    int64_t kprefix[2];
+};
+
 // Buffer placement for cfg. The sweep plan depends on the device (resident workgroups per
 // compute unit), so the per-step partial sums are sized for the largest plan; `plan` and
 // `chunk` are provisional here and fixed by lpc_create.
@@ -127,7 +148,7 @@ Layout plan_layout(const lpc_config &c)
     L.K = 3 * c.n_regions + 6;
     L.storage = c.precision == LPC_PREC_FP64 ? 8 : 4;
     lpc::Geometry g{c.n[0], c.n[1], c.n[2], {c.bc[0], c.bc[1], c.bc[2]}};
-    L.plan = lpc::make_plan(g, 1, 256);
+    L.plan = lpc::make_plan(g, 1, 256, 0);
     const int64_t per_step_max = int64_t(L.K) * lpc::max_sweep_blocks(g) * 8;
     L.staging = L.n < kStagingMax ? L.n : kStagingMax;
     size_t o = 0;
@@ -154,6 +175,11 @@ Layout plan_layout(const lpc_config &c)
     L.off_records = take(size_t(c.max_records) * L.K * 8);
     L.off_staging = take(size_t(L.staging) * 8);
     L.off_scalars = take(kScalars * 8);
+    L.fft_max = fid_of(c) ? fft_length(c.max_records) : 0;
+    L.off_fft = take(size_t(L.fft_max) * 32);                 // two complex buffers
+    L.off_argmax = take(kArgmaxParts * 16 + 64);
+    L.off_profile = take(size_t(std::max(c.n[0], std::max(c.n[1], c.n[2]))) * 8);
+    L.off_list = take(sizeof(SoloTables));
     L.total = o;
     set_chunk(L);
     return L;
@@ -182,6 +208,27 @@ struct lpc_lattice {
     double *records() const { return at<double>(L.off_records); }
     double *staging() const { return at<double>(L.off_staging); }
     double *scalars() const { return at<double>(L.off_scalars); }
+
+    lpc::SweepItem sweep_item(int src) const
+    {
+        lpc::SweepItem it{};
+        it.a = args(src);
+        it.plan = L.plan;
+        return it;
+    }
+
+    lpc::FinalizeItem finalize_item(int64_t row_base) const
+    {
+        lpc::FinalizeItem f{};
+        f.partials = partials();
+        f.records = records();
+        f.nblocks = L.plan.nblocks;
+        f.row_base = row_base;
+        f.K = L.K;
+        return f;
+    }
+
+    SoloTables *solo() const { return at<SoloTables>(L.off_list); }
 
     lpc::StepArgs args(int src) const
     {
@@ -381,7 +428,7 @@ lpc_status lpc_create(const lpc_config *cfg, void *arena, size_t arena_bytes, vo
     {
         lpc::Geometry g{cfg->n[0], cfg->n[1], cfg->n[2], {cfg->bc[0], cfg->bc[1], cfg->bc[2]}};
         const int occ = lpc::sweep_blocks_per_cu(cfg->precision, cfg->track, cfg->n_regions);
-        lat->L.plan = lpc::make_plan(g, occ, cus);
+        lat->L.plan = lpc::make_plan(g, occ, cus, 0);
         set_chunk(lat->L);
     }
     for (int b = 0; b < 2; ++b) {
@@ -395,7 +442,16 @@ lpc_status lpc_create(const lpc_config *cfg, void *arena, size_t arena_bytes, vo
         }
     }
     const size_t ns = size_t(L.n) * L.storage;
-    hipError_t e = hipMemsetAsync(lat->at(L.off_F), 0, ns, lat->stream);
+    SoloTables tables{};
+    tables.item = lat->sweep_item(0);
+    tables.prefix[0] = 0;
+    tables.prefix[1] = lat->L.plan.nblocks;
+    tables.fin = lat->finalize_item(0);
+    tables.kprefix[0] = 0;
+    tables.kprefix[1] = lat->L.K;
+    hipError_t e = hipMemcpy(lat->solo(), &tables, sizeof tables, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(lat->at(L.off_F), 0, ns, lat->stream);
     if (e == hipSuccess && fid_of(*cfg))
         e = hipMemsetAsync(lat->at(L.off_theta), 0, ns, lat->stream);
     if (e == hipSuccess)
@@ -534,19 +590,20 @@ lpc_status lpc_run(lpc_lattice *lat, int64_t n_steps)
                     (long long)n_steps);
     if (lpc_status s = use_device(lat))
         return s;
-    const lpc::SweepPlan &plan = lat->L.plan;
-    const int K = lat->L.K;
+    SoloTables *t = lat->solo();
+    lpc::StepList list{&t->item, t->prefix, 1, lat->L.plan.tx, lat->L.plan.nblocks, 0, 0};
     int64_t left = n_steps;
     while (left > 0) {
         const int64_t c = left < lat->L.chunk ? left : lat->L.chunk;
         for (int64_t s = 0; s < c; ++s) {
-            lpc::StepArgs a = lat->args(lat->cur);
-            a.partials = lat->partials() + s * K * plan.nblocks;
-            LPC_HIP(lpc::launch_step(plan, a, lat->stream));
+            list.parity = lat->cur;
+            list.slot = s;
+            LPC_HIP(lpc::launch_step_list(list, lat->cfg.precision, lat->cfg.track,
+                                          lat->cfg.n_regions, lat->stream));
             lat->cur ^= 1;
         }
-        LPC_HIP(lpc::launch_finalize(lat->partials(), plan.nblocks, K, c,
-                                     lat->records() + (lat->steps_done + 1) * K, lat->stream));
+        LPC_HIP(lpc::launch_finalize_list(&t->fin, t->kprefix, 1, lat->L.K, c,
+                                          lat->steps_done + 1, lat->stream));
         lat->steps_done += c;
         left -= c;
     }
@@ -837,6 +894,390 @@ lpc_status lpc_load_state(lpc_lattice *lat, const void *buf, size_t len)
     LPC_HIP(hipMemcpy(lat->records(), p, size_t(h.rows) * lat->L.K * 8, hipMemcpyHostToDevice));
     lat->steps_done = h.steps_done;
     lat->initialized = true;
+    return ok();
+}
+
+lpc_status lpc_spectrum_length(const lpc_lattice *lat, int64_t *n_fft)
+{
+    if (!lat || !n_fft)
+        return fail(LPC_ERR_ARG, "NULL argument");
+    if (!fid_of(lat->cfg))
+        return fail(LPC_ERR_STATE, "magnetisation is not tracked");
+    *n_fft = fft_length(lat->steps_done + 1);
+    return ok();
+}
+
+namespace {
+
+// Runs the spectrum of `region` on the device; leaves the sorted real/imaginary parts in
+// device memory at *sorted (2 L doubles).
+lpc_status device_spectrum(lpc_lattice *lat, int32_t region, int64_t L, double **sorted)
+{
+    if (!fid_of(lat->cfg))
+        return fail(LPC_ERR_STATE, "magnetisation is not tracked");
+    if (!lat->initialized)
+        return fail(LPC_ERR_STATE, "state not initialised");
+    const int R = lat->cfg.n_regions;
+    if (region < -1 || region >= R)
+        return fail(LPC_ERR_ARG, "region %d outside -1..%d", region, R - 1);
+    const int64_t rows = lat->steps_done + 1;
+    if (L < rows || (L & (L - 1)) != 0 || L > lat->L.fft_max)
+        return fail(LPC_ERR_ARG,
+                    "n_fft = %lld must be a power of two >= %lld samples and <= %lld",
+                    (long long)L, (long long)rows, (long long)lat->L.fft_max);
+    std::vector<double> row0(size_t(lat->L.K));
+    if (lpc_status s = sync(lat))
+        return s;
+    LPC_HIP(hipMemcpy(row0.data(), lat->records(), row0.size() * 8, hipMemcpyDeviceToHost));
+    double c = 0.0, d = 0.0;
+    for (int r = 0; r < R; ++r)
+        if (region < 0 || r == region) {
+            c += row0[2 * r];
+            d += row0[2 * r + 1];
+        }
+    if (c == 0.0 && d == 0.0)
+        return fail(LPC_ERR_STATE, "the FID of region %d starts at zero", region);
+    auto *a = lat->at<double2>(lat->L.off_fft);
+    auto *b = a + lat->L.fft_max;
+    // the sorted output goes to the buffer the last pass did not write
+    int passes = 0;
+    for (int64_t p = 1; p < L; p *= 2)
+        ++passes;
+    double *out = reinterpret_cast<double *>(passes % 2 == 0 ? b : a);
+    LPC_HIP(lpc::launch_fid_spectrum(lat->records(), rows, lat->L.K, R, region, L, a, b, out,
+                                     lat->stream));
+    *sorted = out;
+    return LPC_OK;
+}
+
+}  // namespace
+
+lpc_status lpc_spectrum(lpc_lattice *lat, int32_t region, int64_t n_fft, double *ppm, double *re,
+                        double *im, int64_t cap)
+{
+    if (!lat || !ppm || !re || !im)
+        return fail(LPC_ERR_ARG, "NULL argument");
+    const int64_t L = n_fft == 0 ? fft_length(lat->steps_done + 1) : n_fft;
+    if (cap < L)
+        return fail(LPC_ERR_OOM, "spectrum has %lld points, buffers hold %lld", (long long)L,
+                    (long long)cap);
+    if (lpc_status s = use_device(lat))
+        return s;
+    double *sorted = nullptr;
+    if (lpc_status s = device_spectrum(lat, region, L, &sorted))
+        return s;
+    if (lpc_status s = sync(lat))
+        return s;
+    LPC_HIP(hipMemcpy(re, sorted, size_t(L) * 8, hipMemcpyDeviceToHost));
+    LPC_HIP(hipMemcpy(im, sorted + L, size_t(L) * 8, hipMemcpyDeviceToHost));
+    // frequency axis of the sorted bins: f_j = (j - L/2) / (L dt), in ppm of the Larmor frequency
+    const double step = 1e6 / (double(L) * lat->cfg.dt_s * lat->cfg.larmor_hz);
+    for (int64_t j = 0; j < L; ++j)
+        ppm[j] = double(j - L / 2) * step;
+    return ok();
+}
+
+lpc_status lpc_spectrum_peak(lpc_lattice *lat, int32_t region, double *peak_ppm)
+{
+    if (!lat || !peak_ppm)
+        return fail(LPC_ERR_ARG, "NULL argument");
+    if (lpc_status s = use_device(lat))
+        return s;
+    const int64_t L = fft_length(lat->steps_done + 1);
+    double *sorted = nullptr;
+    if (lpc_status s = device_spectrum(lat, region, L, &sorted))
+        return s;
+    double *pval = lat->at<double>(lat->L.off_argmax);
+    auto *pidx = reinterpret_cast<int64_t *>(pval + kArgmaxParts);
+    auto *where = pidx + kArgmaxParts;
+    LPC_HIP(lpc::launch_argmax(sorted, L, pval, pidx, kArgmaxParts, where, lat->stream));
+    if (lpc_status s = sync(lat))
+        return s;
+    int64_t j = -1;
+    LPC_HIP(hipMemcpy(&j, where, 8, hipMemcpyDeviceToHost));
+    if (j < 0)
+        return fail(LPC_ERR_NONFINITE, "spectrum has no finite maximum");
+    const double step = 1e6 / (double(L) * lat->cfg.dt_s * lat->cfg.larmor_hz);
+    double off = 0.0;
+    if (j > 0 && j < L - 1) {
+        double y[3];
+        LPC_HIP(hipMemcpy(y, sorted + j - 1, 24, hipMemcpyDeviceToHost));
+        // vertex of the parabola through the three highest bins
+        const double den = y[0] - 2.0 * y[1] + y[2];
+        off = den != 0.0 ? 0.5 * (y[0] - y[2]) / den : 0.0;
+    }
+    *peak_ppm = (double(j - L / 2) + off) * step;
+    return ok();
+}
+
+lpc_status lpc_diffusion(lpc_lattice *lat, double *D_m2_s, double *ratio)
+{
+    if (!lat || !D_m2_s || !ratio)
+        return fail(LPC_ERR_ARG, "NULL argument");
+    if (!msd_of(lat->cfg))
+        return fail(LPC_ERR_STATE, "displacement moments are not tracked");
+    if (lat->steps_done < 2)
+        return fail(LPC_ERR_STATE, "the slope needs at least 2 steps");
+    std::vector<double> rec;
+    if (lpc_status s = fetch_records(lat, rec))
+        return s;
+    if (lpc_status s = health(lat, rec))
+        return s;
+    const int K = lat->L.K, R = lat->cfg.n_regions;
+    const int64_t N = lat->steps_done, h = N / 2;
+    auto msd = [&](int64_t t, int a) {
+        double m = 0.0;
+        for (int r = 0; r < R; ++r)
+            m += rec[size_t(t * K + 2 * R + r)];
+        return rec[size_t(t * K + 3 * R + 3 + a)] / m;
+    };
+    const double a2 = lat->cfg.spacing_m * lat->cfg.spacing_m;
+    for (int a = 0; a < 3; ++a) {
+        const double slope = (msd(N, a) - msd(h, a)) / double(N - h);   // lattice units^2 / step
+        D_m2_s[a] = a2 * slope / (2.0 * lat->cfg.dt_s);
+        ratio[a] = lat->cfg.p_hop > 0.0 ? slope / (2.0 * lat->cfg.p_hop) : 0.0;
+    }
+    return ok();
+}
+
+lpc_status lpc_uptake_profile(lpc_lattice *lat, int32_t axis, double *profile, int64_t cap)
+{
+    if (!lat || !profile)
+        return fail(LPC_ERR_ARG, "NULL argument");
+    if (axis < 0 || axis > 2)
+        return fail(LPC_ERR_ARG, "axis %d outside 0..2", axis);
+    if (!lat->initialized)
+        return fail(LPC_ERR_STATE, "state not initialised");
+    const int64_t n = lat->cfg.n[axis];
+    if (cap < n)
+        return fail(LPC_ERR_OOM, "profile has %lld values, buffer holds %lld", (long long)n,
+                    (long long)cap);
+    if (lpc_status s = use_device(lat))
+        return s;
+    lpc::Geometry g{lat->cfg.n[0], lat->cfg.n[1], lat->cfg.n[2],
+                    {lat->cfg.bc[0], lat->cfg.bc[1], lat->cfg.bc[2]}};
+    double *dev = lat->at<double>(lat->L.off_profile);
+    LPC_HIP(lpc::launch_profile(lat->st[lat->cur].rho, g, axis, dev, lat->stream));
+    if (lpc_status s = sync(lat))
+        return s;
+    LPC_HIP(hipMemcpy(profile, dev, size_t(n) * 8, hipMemcpyDeviceToHost));
+    return ok();
+}
+
+}  // extern "C"
+
+struct lpc_batch {
+    std::vector<lpc_lattice *> lats;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    char *arena = nullptr;
+    int32_t precision = 0;
+    uint32_t track = 0;
+    int32_t maxr = 1;
+    lpc::SweepItem *items = nullptr;      // count entries
+    int64_t *prefix = nullptr;            // count + 3 entries (one list per tile width)
+    lpc::FinalizeItem *fin = nullptr;     // count entries
+    int64_t *kprefix = nullptr;           // count + 1 entries
+    hipEvent_t done = nullptr;            // end of the last batch run, awaited by the lattices
+};
+
+namespace {
+
+struct BatchLayout {
+    size_t items, prefix, fin, kprefix, total;
+};
+
+BatchLayout batch_layout(int32_t count)
+{
+    BatchLayout b{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    b.items = take(size_t(count) * sizeof(lpc::SweepItem));
+    b.prefix = take(size_t(count + 3) * 8);
+    b.fin = take(size_t(count) * sizeof(lpc::FinalizeItem));
+    b.kprefix = take(size_t(count + 1) * 8);
+    b.total = o;
+    return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+lpc_status lpc_batch_query_footprint(int32_t count, size_t *bytes)
+{
+    if (count < 1 || !bytes)
+        return fail(LPC_ERR_ARG, "count must be >= 1 and bytes non-NULL");
+    *bytes = batch_layout(count).total;
+    return ok();
+}
+
+lpc_status lpc_batch_create(lpc_lattice *const *lats, int32_t count, void *arena, size_t bytes,
+                            void *stream, lpc_batch **out)
+{
+    if (!lats || count < 1 || !arena || !out)
+        return fail(LPC_ERR_ARG, "NULL argument or empty batch");
+    if (reinterpret_cast<uintptr_t>(arena) % kAlign)
+        return fail(LPC_ERR_ARG, "arena must be %zu-byte aligned", kAlign);
+    const BatchLayout bl = batch_layout(count);
+    if (bytes < bl.total)
+        return fail(LPC_ERR_OOM, "batch arena has %zu bytes, needs %zu", bytes, bl.total);
+    for (int32_t l = 0; l < count; ++l) {
+        if (!lats[l])
+            return fail(LPC_ERR_ARG, "lattice %d is NULL", l);
+        if (lats[l]->cfg.precision != lats[0]->cfg.precision ||
+            lats[l]->cfg.track != lats[0]->cfg.track)
+            return fail(LPC_ERR_ARG, "lattice %d differs in precision or track set", l);
+        if (lats[l]->device != lats[0]->device)
+            return fail(LPC_ERR_ARG, "lattice %d is on another device", l);
+        for (int32_t m = 0; m < l; ++m)
+            if (lats[m] == lats[l])
+                return fail(LPC_ERR_ARG, "lattice %d appears twice", l);
+    }
+    auto *b = new (std::nothrow) lpc_batch;
+    if (!b)
+        return fail(LPC_ERR_OOM, "host allocation failed");
+    b->lats.assign(lats, lats + count);
+    b->stream = static_cast<hipStream_t>(stream);
+    b->device = lats[0]->device;
+    b->arena = static_cast<char *>(arena);
+    b->precision = lats[0]->cfg.precision;
+    b->track = lats[0]->cfg.track;
+    for (lpc_lattice *l : b->lats)
+        b->maxr = std::max(b->maxr, l->cfg.n_regions);
+    b->items = reinterpret_cast<lpc::SweepItem *>(b->arena + bl.items);
+    b->prefix = reinterpret_cast<int64_t *>(b->arena + bl.prefix);
+    b->fin = reinterpret_cast<lpc::FinalizeItem *>(b->arena + bl.fin);
+    b->kprefix = reinterpret_cast<int64_t *>(b->arena + bl.kprefix);
+    if (hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
+        delete b;
+        return fail(LPC_ERR_DEVICE, "hipEventCreateWithFlags failed");
+    }
+    *out = b;
+    return ok();
+}
+
+lpc_status lpc_batch_destroy(lpc_batch *batch)
+{
+    if (!batch)
+        return fail(LPC_ERR_ARG, "batch is NULL");
+    (void)hipStreamSynchronize(batch->stream);
+    (void)hipEventDestroy(batch->done);
+    delete batch;
+    return ok();
+}
+
+lpc_status lpc_batch_run(lpc_batch *batch, const int64_t *n_steps)
+{
+    if (!batch || !n_steps)
+        return fail(LPC_ERR_ARG, "NULL argument");
+    const int32_t count = int32_t(batch->lats.size());
+    for (int32_t l = 0; l < count; ++l) {
+        const lpc_lattice *lat = batch->lats[l];
+        if (n_steps[l] < 0)
+            return fail(LPC_ERR_ARG, "n_steps[%d] is negative", l);
+        if (n_steps[l] > 0 && !lat->initialized)
+            return fail(LPC_ERR_STATE, "lattice %d is not initialised", l);
+        if (lat->steps_done + n_steps[l] > lat->cfg.max_records - 1)
+            return fail(LPC_ERR_STATE, "lattice %d: records hold %lld steps; %lld done, %lld asked",
+                        l, (long long)(lat->cfg.max_records - 1), (long long)lat->steps_done,
+                        (long long)n_steps[l]);
+    }
+    int d = -1;
+    LPC_HIP(hipGetDevice(&d));
+    if (d != batch->device)
+        LPC_HIP(hipSetDevice(batch->device));
+    // the lattices' own streams may still hold work on them
+    for (lpc_lattice *lat : batch->lats)
+        LPC_HIP(hipStreamSynchronize(lat->stream));
+    std::vector<lpc::SweepItem> items;
+    std::vector<int64_t> prefix, kprefix;
+    std::vector<lpc::FinalizeItem> fin;
+    std::vector<int32_t> active;
+    int64_t done = 0;
+    for (;;) {
+        active.clear();
+        int64_t phase_end = INT64_MAX;
+        for (int32_t l = 0; l < count; ++l)
+            if (n_steps[l] > done) {
+                active.push_back(l);
+                phase_end = std::min(phase_end, n_steps[l]);
+            }
+        if (active.empty())
+            break;
+        const int64_t steps = phase_end - done;
+        // work tables of this phase: one list per tile width, then the finalisation list
+        items.clear();
+        prefix.clear();
+        fin.clear();
+        kprefix.assign(1, 0);
+        struct Group {
+            int32_t tile_x, first, n;
+            size_t prefix_at;
+            int64_t total;
+        };
+        std::vector<Group> groups;
+        int64_t chunk = kChunkMax;
+        for (int32_t tx : {64, 32, 16}) {
+            Group gr{tx, int32_t(items.size()), 0, prefix.size(), 0};
+            prefix.push_back(0);
+            for (int32_t l : active) {
+                lpc_lattice *lat = batch->lats[l];
+                if (lat->L.plan.tx != tx)
+                    continue;
+                items.push_back(lat->sweep_item(lat->cur));
+                gr.total += lat->L.plan.nblocks;
+                prefix.push_back(gr.total);
+                ++gr.n;
+            }
+            if (gr.n > 0)
+                groups.push_back(gr);
+        }
+        for (int32_t l : active) {
+            lpc_lattice *lat = batch->lats[l];
+            fin.push_back(lat->finalize_item(lat->steps_done));
+            kprefix.push_back(kprefix.back() + lat->L.K);
+            chunk = std::min(chunk, lat->L.chunk);
+        }
+        LPC_HIP(hipStreamSynchronize(batch->stream));
+        LPC_HIP(hipMemcpyAsync(batch->items, items.data(), items.size() * sizeof(items[0]),
+                               hipMemcpyHostToDevice, batch->stream));
+        LPC_HIP(hipMemcpyAsync(batch->prefix, prefix.data(), prefix.size() * 8,
+                               hipMemcpyHostToDevice, batch->stream));
+        LPC_HIP(hipMemcpyAsync(batch->fin, fin.data(), fin.size() * sizeof(fin[0]),
+                               hipMemcpyHostToDevice, batch->stream));
+        LPC_HIP(hipMemcpyAsync(batch->kprefix, kprefix.data(), kprefix.size() * 8,
+                               hipMemcpyHostToDevice, batch->stream));
+        LPC_HIP(hipStreamSynchronize(batch->stream));
+        const int64_t total_k = kprefix.back();
+        for (int64_t s0 = 0; s0 < steps; s0 += chunk) {
+            const int64_t c = std::min(chunk, steps - s0);
+            for (int64_t s = 0; s < c; ++s) {
+                for (const Group &gr : groups) {
+                    lpc::StepList list{batch->items + gr.first, batch->prefix + gr.prefix_at,
+                                       gr.n, gr.tile_x, gr.total, int32_t((s0 + s) & 1), s};
+                    LPC_HIP(lpc::launch_step_list(list, batch->precision, batch->track,
+                                                  batch->maxr, batch->stream));
+                }
+            }
+            LPC_HIP(lpc::launch_finalize_list(batch->fin, batch->kprefix, int32_t(active.size()),
+                                              total_k, c, s0 + 1, batch->stream));
+        }
+        for (int32_t l : active) {
+            lpc_lattice *lat = batch->lats[l];
+            lat->steps_done += steps;
+            lat->cur ^= int(steps & 1);
+        }
+        done = phase_end;
+    }
+    // later work and reads on each lattice's own stream come after the batch
+    LPC_HIP(hipEventRecord(batch->done, batch->stream));
+    for (lpc_lattice *lat : batch->lats)
+        LPC_HIP(hipStreamWaitEvent(lat->stream, batch->done, 0));
     return ok();
 }
 

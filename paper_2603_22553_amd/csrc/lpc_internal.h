@@ -21,7 +21,7 @@ struct Geometry {
     int32_t bc[3];  // 0 periodic, 1 closed
 };
 
-// Launch shape of the sweep: a 1-D grid of workgroups, each owning a TX x TY x-y tile
+// Launch shape of the sweep: a 1-D grid of workgroups, each owning a tx x ty x-y tile
 // and a run of zc planes. Blocks are renumbered so that each XCD gets a contiguous
 // range of tiles (hardware dispatch is round-robin over the 8 XCDs).
 struct SweepPlan {
@@ -47,12 +47,48 @@ struct StepArgs {
 
 // Upper bound on the workgroups of any plan for g (sizes the per-step partial sums).
 int64_t max_sweep_blocks(const Geometry &g);
-// Plan for g given the resident sweep workgroups per compute unit and the compute units.
-SweepPlan make_plan(const Geometry &g, int32_t blocks_per_cu, int32_t cus);
+// Plan for g given the resident sweep workgroups per compute unit and the compute units;
+// tile_x 64, 32 or 16 fixes the tile width, anything else picks the least x padding.
+SweepPlan make_plan(const Geometry &g, int32_t blocks_per_cu, int32_t cus, int32_t tile_x);
 // Resident sweep workgroups per compute unit for this precision, track set and regions.
 int sweep_blocks_per_cu(int32_t precision, uint32_t track, int32_t R);
 
-hipError_t launch_step(const SweepPlan &plan, const StepArgs &a, hipStream_t s);
+// One entry of a sweep work list: a lattice's step arguments (views of the parity-0 step)
+// and its plan.
+struct SweepItem {
+    StepArgs a;
+    SweepPlan plan;
+};
+
+// A work list in device memory: items[0, n_items) whose workgroups are numbered by the
+// exclusive prefix sums prefix[0, n_items] of their plans' nblocks (total = prefix[n_items]),
+// all with tiles tile_x wide; one launch steps them all with the given parity, writing
+// partial sums into step slot `slot` of each lattice's partials.
+struct StepList {
+    const SweepItem *items;
+    const int64_t *prefix;
+    int32_t n_items;
+    int32_t tile_x;
+    int64_t total;
+    int32_t parity;
+    int64_t slot;
+};
+
+// Records of a finalisation: partials [steps][K][nblocks] of one lattice into rows
+// row_base + first_row + s of its records.
+struct FinalizeItem {
+    const double *partials;
+    double *records;
+    int64_t nblocks;
+    int64_t row_base;
+    int32_t K;
+    int32_t pad;
+};
+
+hipError_t launch_step_list(const StepList &list, int32_t precision, uint32_t track, int32_t maxr,
+                            hipStream_t s);
+hipError_t launch_finalize_list(const FinalizeItem *items, const int64_t *kprefix, int32_t n_items,
+                                int64_t total_k, int64_t steps, int64_t first_row, hipStream_t s);
 hipError_t launch_record(const SweepPlan &plan, const StepArgs &a, hipStream_t s);
 hipError_t launch_finalize(const double *partials, int64_t nblocks, int32_t K, int64_t steps,
                            double *records_out, hipStream_t s);
@@ -69,6 +105,21 @@ hipError_t launch_boltzmann_weights(int32_t precision, const void *F, double Fmi
 // rho_i = w_i * scale_num / (*Z) in place.
 hipError_t launch_boltzmann_scale(double *w, int64_t n, double numer, const double *Z,
                                   hipStream_t s);
+
+// Spectrum of the recorded FID: normalised, zero-filled series in buf_a, Stockham FFT
+// ping-ponging between buf_a and buf_b (L complex values each, L a power of two), then
+// the ascending-frequency real parts in sorted[0, L) and imaginary parts in
+// sorted[L, 2L); sorted == nullptr writes them into whichever buffer is free. Returns
+// through *where the buffer holding the sorted output (when sorted is nullptr).
+hipError_t launch_fid_spectrum(const double *records, int64_t rows, int32_t K, int32_t R,
+                               int32_t region, int64_t L, double2 *buf_a, double2 *buf_b,
+                               double *sorted, hipStream_t s);
+// Index of the first maximum of v[0, n) into *out (nparts workgroup partials).
+hipError_t launch_argmax(const double *v, int64_t n, double *pval, int64_t *pidx, int32_t nparts,
+                         int64_t *out, hipStream_t s);
+// Population summed over the planes perpendicular to `axis`.
+hipError_t launch_profile(const double *rho, const Geometry &g, int32_t axis, double *profile,
+                          hipStream_t s);
 
 // Plain copy of n16 16-byte words (calibration kernel).
 hipError_t launch_stream_copy(const void *src, void *dst, int64_t n16, hipStream_t s);

@@ -60,12 +60,18 @@ __host__ __device__ inline View<S> typed(const StateView &v)
     return t;
 }
 
+// Device global memory. Pointers that come from a work list in memory (not from kernel
+// arguments) are generic to the compiler; addressing them as global keeps the loads off the
+// flat path, whose completion would also be awaited by every LDS wait.
+#define LPC_GLOBAL __attribute__((address_space(1)))
+
 // Element at a 32-bit byte offset from a workgroup-uniform base: the base lives in scalar
 // registers and the per-lane offset in one vector register.
 template <typename T>
 __device__ inline T ld(const T *base, uint32_t boff)
 {
-    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + boff);
+    const LPC_GLOBAL char *b = (const LPC_GLOBAL char *)base;
+    return *(const LPC_GLOBAL T *)(b + boff);
 }
 
 // State arrays are written once per step and not read again within it: stream them past
@@ -73,7 +79,8 @@ __device__ inline T ld(const T *base, uint32_t boff)
 template <typename T>
 __device__ inline void st(T *base, uint32_t boff, T v)
 {
-    __builtin_nontemporal_store(v, reinterpret_cast<T *>(reinterpret_cast<char *>(base) + boff));
+    LPC_GLOBAL char *b = (LPC_GLOBAL char *)base;
+    __builtin_nontemporal_store(v, (LPC_GLOBAL T *)(b + boff));
 }
 
 // Population flux of a link with both products rounded separately, so that the value
@@ -399,12 +406,10 @@ struct TileLds {
 
 // ---------------------------------------------------------------------------- kernels
 
-constexpr int kTileX = 64;
-
-#ifndef LPC_TILE_Y
-#define LPC_TILE_Y 4
-#endif
-constexpr int kTileY = LPC_TILE_Y;
+// Workgroups are 256 threads: one thread per column of a TX x (256 / TX) tile of x-y
+// columns. TX is 64 for wide lattices (a wave covers one 64-site row) and 32 or 16 for
+// narrow ones, so that small boxes do not leave most lanes idle.
+constexpr int kThreads = 256;
 
 __device__ inline void tile_coords(const SweepPlan &p, int64_t blk, int &bx, int &by, int &bz)
 {
@@ -425,7 +430,7 @@ struct TileThread {
 // One z-plane of the tile: stage it in LDS buffer `L` (own site + halo site), wait for the
 // whole tile, prefetch plane z+2 (own column) into `nx2` and the halo of plane z+1 into
 // `halo`, then update every site of the plane from LDS (x, y) and registers (z).
-template <typename S, bool FID, bool MSD, int MAXR, int TY, typename LDS>
+template <typename S, bool FID, bool MSD, int MAXR, int TX, typename LDS>
 __device__ __forceinline__ void plane_step(LDS &L, const StepArgs &a, const TileThread &th,
                                            const View<S> &src, const View<S> &dst, const S *F,
                                            const S *TH, int64_t plane, int z, int z1,
@@ -435,7 +440,7 @@ __device__ __forceinline__ void plane_step(LDS &L, const StepArgs &a, const Tile
                                            Cell<S, FID, MSD> &nx2, Cell<S, FID, MSD> &halo,
                                            RecAcc<MAXR> &acc)
 {
-    constexpr int COLS = kTileX + 2;
+    constexpr int COLS = TX + 2;
     const Geometry &g = a.g;
     const bool zper = g.bc[2] == 0;
     if (th.act)
@@ -494,7 +499,7 @@ __device__ __forceinline__ void plane_step(LDS &L, const StepArgs &a, const Tile
 #define LPC_MIN_WAVES 1
 #endif
 
-// One step over a 64 x TY tile of x-y columns and the workgroup's run of z-planes. Each
+// One step over a TX x TY tile of x-y columns and the workgroup's run of z-planes. Each
 // thread owns one column and keeps planes z-1, z, z+1 of it in registers, with plane z+2
 // in flight; the four register sets rotate roles from plane to plane, so no move forces
 // an early wait on a prefetch. The x and y neighbours of plane z come from an LDS image of
@@ -503,18 +508,14 @@ __device__ __forceinline__ void plane_step(LDS &L, const StepArgs &a, const Tile
 // on periodic axes, absent across closed faces) are spread over threads, one site each,
 // and fetched one plane ahead. Plane offsets are workgroup-uniform; each thread keeps only
 // the 32-bit byte offsets of its column.
-template <typename S, bool FID, bool MSD, int MAXR, int TY>
-__global__ __launch_bounds__(kTileX *TY, LPC_MIN_WAVES) void k_sweep_tile(StepArgs a, SweepPlan p,
-                                                                         int64_t padded)
+template <typename S, bool FID, bool MSD, int MAXR, int TX>
+__device__ __forceinline__ void sweep_tile(const StepArgs &a, const SweepPlan &p, int64_t blk)
 {
-    constexpr int TX = kTileX, COLS = TX + 2, NL = COLS * (TY + 2);
+    constexpr int TY = kThreads / TX, COLS = TX + 2, NL = COLS * (TY + 2);
     static_assert(TX * TY >= 2 * TX + 2 * TY, "one halo site per thread");
     using C = Cell<S, FID, MSD>;
     __shared__ TileLds<S, FID, MSD, NL> L0, L1;
-    __shared__ double red[TY * (3 * MAXR + 6)];
-    const int64_t blk = logical_block(blockIdx.x, padded);
-    if (blk >= p.nblocks)
-        return;
+    __shared__ double red[(kThreads / kWave) * (3 * MAXR + 6)];
     const Geometry &g = a.g;
     int bx, by, bz;
     tile_coords(p, blk, bx, by, bz);
@@ -592,19 +593,50 @@ __global__ __launch_bounds__(kTileX *TY, LPC_MIN_WAVES) void k_sweep_tile(StepAr
     // roles (prv, cur, nxt, in-flight) rotate through w0..w3 with period 4; LDS buffers
     // alternate with period 2
     for (int z = z0; z < z1; z += 4) {
-        plane_step<S, FID, MSD, MAXR, TY>(L0, a, th, src, dst, F, TH, plane, z, z1, w0, w1, w2, w3, halo, acc);
+        plane_step<S, FID, MSD, MAXR, TX>(L0, a, th, src, dst, F, TH, plane, z, z1, w0, w1, w2, w3, halo, acc);
         if (z + 1 >= z1)
             break;
-        plane_step<S, FID, MSD, MAXR, TY>(L1, a, th, src, dst, F, TH, plane, z + 1, z1, w1, w2, w3, w0, halo, acc);
+        plane_step<S, FID, MSD, MAXR, TX>(L1, a, th, src, dst, F, TH, plane, z + 1, z1, w1, w2, w3, w0, halo, acc);
         if (z + 2 >= z1)
             break;
-        plane_step<S, FID, MSD, MAXR, TY>(L0, a, th, src, dst, F, TH, plane, z + 2, z1, w2, w3, w0, w1, halo, acc);
+        plane_step<S, FID, MSD, MAXR, TX>(L0, a, th, src, dst, F, TH, plane, z + 2, z1, w2, w3, w0, w1, halo, acc);
         if (z + 3 >= z1)
             break;
-        plane_step<S, FID, MSD, MAXR, TY>(L1, a, th, src, dst, F, TH, plane, z + 3, z1, w3, w0, w1, w2, halo, acc);
+        plane_step<S, FID, MSD, MAXR, TX>(L1, a, th, src, dst, F, TH, plane, z + 3, z1, w3, w0, w1, w2, halo, acc);
     }
     __syncthreads();
-    block_reduce<MAXR, TY>(acc, a.R, a.K, a.partials, p.nblocks, blk, red);
+    block_reduce<MAXR, kThreads / kWave>(acc, a.R, a.K, a.partials, p.nblocks, blk, red);
+}
+
+// One step of every lattice in a work list: workgroup w (after the XCD renumbering) runs
+// tile w - prefix[l] of item l, prefix[l] <= w < prefix[l + 1]. The items hold the views
+// of the step with parity 0; parity 1 swaps source and destination. Each lattice keeps its
+// own plan, so a lattice gives the same bits alone (a list of one) and in any batch.
+template <typename S, bool FID, bool MSD, int MAXR, int TX>
+__global__ __launch_bounds__(kThreads, LPC_MIN_WAVES) void k_sweep_tile(
+    const SweepItem *__restrict__ items, const int64_t *__restrict__ prefix, int32_t n_items,
+    int64_t total, int64_t padded, int32_t parity, int64_t slot)
+{
+    const int64_t w = logical_block(blockIdx.x, padded);
+    if (w >= total)
+        return;
+    int lo = 0, hi = n_items - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (prefix[mid] <= w)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    StepArgs a = items[lo].a;
+    const SweepPlan p = items[lo].plan;
+    if (parity) {
+        const StateView t = a.src;
+        a.src = a.dst;
+        a.dst = t;
+    }
+    a.partials += slot * a.K * p.nblocks;
+    sweep_tile<S, FID, MSD, MAXR, TX>(a, p, w - prefix[lo]);
 }
 
 template <typename S, bool FID, bool MSD, int MAXR>
@@ -627,18 +659,17 @@ __device__ inline void record_site(const StepArgs &a, const View<S> &v, int64_t 
 }
 
 // Record contributions of the current state (no step), on the same tiles as the sweep.
-template <typename S, bool FID, bool MSD, int MAXR, int TY>
-__global__ __launch_bounds__(kTileX *TY) void k_record_tile(StepArgs a, SweepPlan p,
-                                                              int64_t padded)
+template <typename S, bool FID, bool MSD, int MAXR>
+__global__ __launch_bounds__(kThreads) void k_record_tile(StepArgs a, SweepPlan p, int64_t padded)
 {
-    __shared__ double red[TY * (3 * MAXR + 6)];
+    __shared__ double red[(kThreads / kWave) * (3 * MAXR + 6)];
     const int64_t blk = logical_block(blockIdx.x, padded);
     if (blk >= p.nblocks)
         return;
     int bx, by, bz;
     tile_coords(p, blk, bx, by, bz);
-    const int x = bx * kTileX + static_cast<int>(threadIdx.x) % kTileX;
-    const int y = by * TY + static_cast<int>(threadIdx.x) / kTileX;
+    const int x = bx * p.tx + static_cast<int>(threadIdx.x) % p.tx;
+    const int y = by * p.ty + static_cast<int>(threadIdx.x) / p.tx;
     const View<S> src = typed<S>(a.src);
     RecAcc<MAXR> acc;
     acc.zero();
@@ -649,15 +680,12 @@ __global__ __launch_bounds__(kTileX *TY) void k_record_tile(StepArgs a, SweepPla
         for (int z = bz * p.zc; z < z1; ++z)
             record_site<S, FID, MSD, MAXR>(a, src, col + plane * z, acc);
     }
-    block_reduce<MAXR, TY>(acc, a.R, a.K, a.partials, p.nblocks, blk, red);
+    block_reduce<MAXR, kThreads / kWave>(acc, a.R, a.K, a.partials, p.nblocks, blk, red);
 }
 
-__global__ __launch_bounds__(256) void k_finalize(const double *partials, int64_t nblocks, int K,
-                                                  double *out)
+// Sum of one record entry over the workgroup partials p[0, nblocks), in a fixed order.
+__device__ inline double partial_sum(const double *p, int64_t nblocks, double *w)
 {
-    __shared__ double w[4];
-    const int s = blockIdx.x / K, k = blockIdx.x % K;
-    const double *p = partials + (static_cast<int64_t>(s) * K + k) * nblocks;
     double v = 0.0;
     for (int64_t b = threadIdx.x; b < nblocks; b += 256)
         v += p[b];
@@ -665,8 +693,42 @@ __global__ __launch_bounds__(256) void k_finalize(const double *partials, int64_
     if (threadIdx.x % kWave == 0)
         w[threadIdx.x / kWave] = v;
     __syncthreads();
+    return ((w[0] + w[1]) + w[2]) + w[3];
+}
+
+__global__ __launch_bounds__(256) void k_finalize(const double *partials, int64_t nblocks, int K,
+                                                  double *out)
+{
+    __shared__ double w[4];
+    const int s = blockIdx.x / K, k = blockIdx.x % K;
+    const double t = partial_sum(partials + (static_cast<int64_t>(s) * K + k) * nblocks, nblocks, w);
     if (threadIdx.x == 0)
-        out[static_cast<int64_t>(s) * K + k] = ((w[0] + w[1]) + w[2]) + w[3];
+        out[static_cast<int64_t>(s) * K + k] = t;
+}
+
+// Records of `steps` steps of every lattice in a list: workgroup (s, e) with
+// kprefix[l] <= e < kprefix[l + 1] writes entry e - kprefix[l] of row first_row + s of
+// lattice l (first_row counted from the lattice's own row base).
+__global__ __launch_bounds__(256) void k_finalize_list(const FinalizeItem *__restrict__ items,
+                                                       const int64_t *__restrict__ kprefix,
+                                                       int32_t n_items, int64_t total_k,
+                                                       int64_t first_row)
+{
+    __shared__ double w[4];
+    const int64_t s = blockIdx.x / total_k, e = blockIdx.x % total_k;
+    int lo = 0, hi = n_items - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (kprefix[mid] <= e)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const FinalizeItem it = items[lo];
+    const int64_t k = e - kprefix[lo];
+    const double t = partial_sum(it.partials + (s * it.K + k) * it.nblocks, it.nblocks, w);
+    if (threadIdx.x == 0)
+        it.records[(it.row_base + first_row + s) * it.K + k] = t;
 }
 
 template <typename S>
@@ -743,20 +805,32 @@ int grid_for(int64_t n, int threads)
 
 // ---------------------------------------------------------------------------- dispatch
 
-template <bool RECORD_ONLY>
-struct TileLauncher {
+struct RecordLauncher {
     template <typename S, bool FID, bool MSD, int MAXR>
     static hipError_t go(const SweepPlan &p, const StepArgs &a, hipStream_t s)
     {
         const int64_t padded = (p.nblocks + 7) / 8 * 8;
-        if (RECORD_ONLY)
-            hipLaunchKernelGGL((k_record_tile<S, FID, MSD, MAXR, kTileY>),
-                               dim3(static_cast<unsigned>(padded)), dim3(kTileX * kTileY), 0, s,
-                               a, p, padded);
+        hipLaunchKernelGGL((k_record_tile<S, FID, MSD, MAXR>), dim3(static_cast<unsigned>(padded)),
+                           dim3(kThreads), 0, s, a, p, padded);
+        return hipGetLastError();
+    }
+};
+
+struct ListLauncher {
+    template <typename S, bool FID, bool MSD, int MAXR>
+    static hipError_t go(const SweepPlan &, const StepArgs &, hipStream_t s, const StepList *L)
+    {
+        const int64_t padded = (L->total + 7) / 8 * 8;
+        const dim3 grid(static_cast<unsigned>(padded)), block(kThreads);
+        if (L->tile_x == 64)
+            hipLaunchKernelGGL((k_sweep_tile<S, FID, MSD, MAXR, 64>), grid, block, 0, s, L->items,
+                               L->prefix, L->n_items, L->total, padded, L->parity, L->slot);
+        else if (L->tile_x == 32)
+            hipLaunchKernelGGL((k_sweep_tile<S, FID, MSD, MAXR, 32>), grid, block, 0, s, L->items,
+                               L->prefix, L->n_items, L->total, padded, L->parity, L->slot);
         else
-            hipLaunchKernelGGL((k_sweep_tile<S, FID, MSD, MAXR, kTileY>),
-                               dim3(static_cast<unsigned>(padded)), dim3(kTileX * kTileY), 0, s,
-                               a, p, padded);
+            hipLaunchKernelGGL((k_sweep_tile<S, FID, MSD, MAXR, 16>), grid, block, 0, s, L->items,
+                               L->prefix, L->n_items, L->total, padded, L->parity, L->slot);
         return hipGetLastError();
     }
 };
@@ -796,25 +870,45 @@ hipError_t by_precision(const SweepPlan &p, const StepArgs &a, hipStream_t s, X.
 
 }  // namespace
 
-int64_t max_sweep_blocks(const Geometry &g)
+// Tile width for a lattice of nx columns: the least padding in x, ties to the wider tile.
+int32_t tile_width(int32_t nx)
 {
-    const int64_t gx = (g.nx + kTileX - 1) / kTileX, gy = (g.ny + kTileY - 1) / kTileY;
-    const int64_t tiles = gx * gy;
-    int64_t gz = std::max<int64_t>((g.nz + 7) / 8, (8192 + tiles - 1) / tiles);
-    return tiles * std::min<int64_t>(g.nz, gz);
+    int32_t best = 64;
+    int64_t best_pad = -1;
+    for (int32_t tx : {64, 32, 16}) {
+        const int64_t pad = (nx + tx - 1) / tx * int64_t(tx);
+        if (best_pad < 0 || pad < best_pad) {
+            best_pad = pad;
+            best = tx;
+        }
+    }
+    return best;
 }
 
-SweepPlan make_plan(const Geometry &g, int32_t blocks_per_cu, int32_t cus)
+int64_t max_sweep_blocks(const Geometry &g)
+{
+    int64_t most = 0;
+    for (int32_t tx : {64, 32, 16}) {
+        const int32_t ty = kThreads / tx;
+        const int64_t tiles = int64_t((g.nx + tx - 1) / tx) * ((g.ny + ty - 1) / ty);
+        const int64_t gz = std::max<int64_t>((g.nz + 7) / 8, (8192 + tiles - 1) / tiles);
+        most = std::max(most, tiles * std::min<int64_t>(g.nz, gz));
+    }
+    return most;
+}
+
+SweepPlan make_plan(const Geometry &g, int32_t blocks_per_cu, int32_t cus, int32_t tile_x)
 {
     SweepPlan p{};
     p.kernel = 1;
-    p.tx = kTileX;
-    p.ty = kTileY;
+    p.tx = tile_x == 64 || tile_x == 32 || tile_x == 16 ? tile_x : tile_width(g.nx);
+    p.ty = kThreads / p.tx;
     p.gx = (g.nx + p.tx - 1) / p.tx;
     p.gy = (g.ny + p.ty - 1) / p.ty;
     const int64_t tiles = static_cast<int64_t>(p.gx) * p.gy;
     const int64_t conc = std::max(1, blocks_per_cu) * static_cast<int64_t>(std::max(1, cus));
-    const int64_t gz_max = max_sweep_blocks(g) / tiles;
+    const int64_t gz_cap = std::max<int64_t>((g.nz + 7) / 8, (8192 + tiles - 1) / tiles);
+    const int64_t gz_max = std::min<int64_t>(g.nz, gz_cap);
     // Pick the z-chunk: every resident slot busy until the end (greedy makespan of the
     // chunks against the ideal), few extra planes per chunk (each chunk re-reads the two
     // planes around it, mostly from cache), and a few rounds to absorb uneven progress.
@@ -847,8 +941,8 @@ struct OccupancyQuery {
     static hipError_t go(const SweepPlan &, const StepArgs &, hipStream_t, int *out)
     {
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            out, reinterpret_cast<const void *>(&k_sweep_tile<S, FID, MSD, MAXR, kTileY>),
-            kTileX * kTileY, 0);
+            out, reinterpret_cast<const void *>(&k_sweep_tile<S, FID, MSD, MAXR, 64>), kThreads,
+            0);
     }
 };
 
@@ -865,14 +959,31 @@ int sweep_blocks_per_cu(int32_t precision, uint32_t track, int32_t R)
     return n;
 }
 
-hipError_t launch_step(const SweepPlan &plan, const StepArgs &a, hipStream_t s)
+hipError_t launch_step_list(const StepList &L, int32_t precision, uint32_t track, int32_t maxr,
+                            hipStream_t s)
 {
-    return by_precision<TileLauncher<false>>(plan, a, s);
+    if (L.total <= 0)
+        return hipSuccess;
+    StepArgs a{};
+    a.precision = precision;
+    a.track = track;
+    a.R = maxr;
+    return by_precision<ListLauncher>(SweepPlan{}, a, s, &L);
 }
 
 hipError_t launch_record(const SweepPlan &plan, const StepArgs &a, hipStream_t s)
 {
-    return by_precision<TileLauncher<true>>(plan, a, s);
+    return by_precision<RecordLauncher>(plan, a, s);
+}
+
+hipError_t launch_finalize_list(const FinalizeItem *items, const int64_t *kprefix, int32_t n_items,
+                                int64_t total_k, int64_t steps, int64_t first_row, hipStream_t s)
+{
+    if (steps <= 0 || total_k <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_finalize_list, dim3(static_cast<unsigned>(steps * total_k)), dim3(256), 0,
+                       s, items, kprefix, n_items, total_k, first_row);
+    return hipGetLastError();
 }
 
 hipError_t launch_finalize(const double *partials, int64_t nblocks, int32_t K, int64_t steps,

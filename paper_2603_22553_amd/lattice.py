@@ -201,6 +201,39 @@ class Lattice:
         N.call("lpc_read_uptake", self.handle, _ptr(out), rows, ctypes.byref(got))
         return out
 
+    # -------------------------------------------------------------- post-processing
+    def spectrum(self, region=None, n_fft=0):
+        """(ppm, complex spectrum) in ascending frequency, Eq. (9), computed on the device."""
+        L = ctypes.c_int64()
+        if n_fft == 0:
+            N.call("lpc_spectrum_length", self.handle, ctypes.byref(L))
+            n_fft = L.value
+        ppm = np.empty(n_fft)
+        re = np.empty(n_fft)
+        im = np.empty(n_fft)
+        N.call("lpc_spectrum", self.handle, -1 if region is None else int(region), int(n_fft),
+               _ptr(ppm), _ptr(re), _ptr(im), n_fft)
+        return ppm, re + 1j * im
+
+    def peak_ppm(self, region=None) -> float:
+        v = ctypes.c_double()
+        N.call("lpc_spectrum_peak", self.handle, -1 if region is None else int(region),
+               ctypes.byref(v))
+        return float(v.value)
+
+    def diffusion(self):
+        """(D per axis in m^2/s, D / D_bulk per axis)."""
+        D = np.empty(3)
+        r = np.empty(3)
+        N.call("lpc_diffusion", self.handle, _ptr(D), _ptr(r))
+        return D, r
+
+    def uptake_profile(self, axis=0) -> np.ndarray:
+        n = self.shape_xyz[axis] if 0 <= axis < 3 else 1   # the library validates the axis
+        out = np.empty(n)
+        N.call("lpc_uptake_profile", self.handle, int(axis), _ptr(out), n)
+        return out
+
     def check(self):
         N.call("lpc_check", self.handle)
 
@@ -216,3 +249,60 @@ class Lattice:
     def load_state(self, blob: bytes):
         buf = ctypes.create_string_buffer(blob, len(blob))
         N.call("lpc_load_state", self.handle, buf, len(blob))
+
+
+def batch_footprint(count: int) -> int:
+    b = ctypes.c_size_t()
+    N.call("lpc_batch_query_footprint", int(count), ctypes.byref(b))
+    return int(b.value)
+
+
+class Batch:
+    """Lattices stepped together: one launch per step and tile width covers every lattice.
+
+    Each lattice ends bit for bit as if it had been run alone (it keeps its own tiles and
+    reduction order). The lattices must outlive the batch.
+    """
+
+    def __init__(self, lattices, stream=None, device=None):
+        self.lattices = list(lattices)
+        if not self.lattices:
+            raise ValueError("empty batch")
+        self.device = torch.device(device) if device is not None else self.lattices[0].device
+        nbytes = batch_footprint(len(self.lattices))
+        self.arena = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        handles = (ctypes.c_void_p * len(self.lattices))(*[l.handle.value for l in self.lattices])
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            N.call("lpc_batch_create", handles, len(self.lattices),
+                   ctypes.c_void_p(self.arena.data_ptr()), nbytes,
+                   ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        self._h = h
+
+    def run(self, n_steps):
+        """n_steps: one count per lattice (or a single int for all)."""
+        if np.isscalar(n_steps):
+            n_steps = [int(n_steps)] * len(self.lattices)
+        a = np.ascontiguousarray(n_steps, dtype=np.int64)
+        if a.size != len(self.lattices):
+            raise ValueError("one step count per lattice")
+        N.call("lpc_batch_run", self._h, _ptr(a))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            N.call("lpc_batch_destroy", self._h)
+            self._h = None
+            self.arena = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
