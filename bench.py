@@ -1,15 +1,17 @@
 """Benchmark of the lattice sweep on one MI355X.
 
-Workload: one 256^3 periodic box holding a carbon particle of radius 112 sites (pore
-field correlation length 8 sites, widths 0.7-2.0 nm), uniform start, FID and MSD moments
-recorded every step; run once on the FP64 path and once on the mixed path (float storage,
-double arithmetic and sums). A step is one time step of the whole sweep: hop
+Default workload (the headline line): one 256^3 periodic box holding a carbon particle of
+radius 112 sites (pore-field correlation length 8 sites, widths 0.7-2.0 nm), uniform start,
+FID and MSD moments recorded every step, run once on the FP64 path and once on the mixed
+path (float storage, double sums). A step is one time step of the whole sweep: hop
 probabilities, population, magnetisation and moment updates, boundary handling and the
-per-step FP64 sums. Inputs are resident in HBM before the timed region starts.
+per-step FP64 sums; the spectrum, its peak and the diffusion coefficients are computed on
+the device once at the end of the timed run. Inputs are resident in HBM before timing.
 
-Prints one JSON line: GSU/s (10^9 site-updates per second) of the FP64 path as `value`,
-the mixed path beside it, the HBM roofline of the sweep kernel and the CPU oracle timed
-on a bounded sample of the same workload.
+Other workloads (--workload): `batch` (512 particles of radius 8-48 in one batched sweep,
+against the same particles run one at a time), `film` (2048 x 256 x 256 supercapacitor
+film, closed in x) and `serve` (Poisson arrivals of spectrum requests through the
+continuous-batching server). Each prints one JSON line.
 """
 from __future__ import annotations
 
@@ -28,6 +30,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 SWEEP_SRC = os.path.join(ROOT, "paper_2603_22553_amd", "csrc", "sweep.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_256cubed_hbm_traffic.md")
+METRIC = "Glattice-site-updates/s (GSU/s) and fraction of HBM roofline"
 
 
 def bytes_per_site_update(precision: str, track=("fid", "msd"), n_regions: int = 2) -> int:
@@ -65,8 +68,31 @@ def measured_traffic(precision: str):
     return float(m.group(1)) if m else None
 
 
-def run_gpu(f, precision, steps, warmup, track=("fid", "msd")):
+def roofline(n_sites, precision, ms_step, track=("fid", "msd"), n_regions=2):
+    b = bytes_per_site_update(precision, track, n_regions)
+    ach = n_sites * b / (ms_step * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(precision),
+            "bytes_per_site_update": b}
+
+
+def timed(stream, fn):
+    """Runs fn() between two events recorded on `stream`; returns (result, milliseconds)."""
     import torch
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    out = fn()
+    t1.record(stream)
+    t1.synchronize()
+    torch.cuda.synchronize()
+    return out, t0.elapsed_time(t1)
+
+
+# ------------------------------------------------------------------- single large particle
+
+def run_particle(f, precision, steps, warmup, track=("fid", "msd")):
     from paper_2603_22553_amd.lattice import Lattice
     lat = Lattice(f.shape_xyz, precision=precision, track=track, n_regions=f.n_regions,
                   max_records=steps + warmup + 1)
@@ -74,27 +100,17 @@ def run_gpu(f, precision, steps, warmup, track=("fid", "msd")):
     lat.init_state("uniform")
     lat.run(warmup)
     lat.synchronize()
-    torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    wall0 = time.perf_counter()
-    t0.record(lat.stream)
-    lat.run(steps)
-    t1.record(lat.stream)
-    t1.synchronize()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms = t0.elapsed_time(t1)
-    lat.check()                    # finite FID, mass conserved to 1e-12
-    mass, msd, _ = lat.moments()
-    out = {
-        "ms": ms,
-        "wall_s": wall,
-        "gsu_s": f.n_sites * steps / (ms * 1e-3) / 1e9,
-        "mass_drift": float(abs(mass[-1] / mass[0] - 1.0)),
-        "msd_last": [float(v) for v in msd[-1]],
-        "plan_blocks": None,
-    }
+
+    def work():
+        lat.run(steps)
+        return lat.peak_ppm(), lat.diffusion()
+
+    (peak, (D, ratio)), ms = timed(lat.stream, work)
+    lat.check()                    # finite FID, population conserved to 1e-12
+    mass = lat.moments()[0]
+    out = {"ms": ms, "gsu_s": f.n_sites * steps / (ms * 1e-3) / 1e9,
+           "mass_drift": float(abs(mass[-1] / mass[0] - 1.0)), "peak_ppm": peak,
+           "D_over_Dbulk": [round(float(v), 6) for v in ratio], "plan": lat.describe()}
     lat.close()
     return out
 
@@ -105,78 +121,277 @@ def cpu_baseline(f, steps):
     t = time.perf_counter()
     oracle.run(f.F, f.delta, f.region, f.n_regions, steps)
     dt = time.perf_counter() - t
-    return {"value": f.n_sites * steps / dt / 1e9, "unit": "GSU/s", "cores": oracle.threads(),
-            "kind": "oracle",
-            "sample": f"{steps} steps of the 256^3 particle lattice, FP64, FID + MSD, "
-                      f"{dt:.1f} s"}
+    return {"value": round(f.n_sites * steps / dt / 1e9, 5), "unit": "GSU/s",
+            "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{steps} steps of the same 256^3 particle lattice (FP64, FID + MSD, "
+                      f"{f.n_sites * steps:.3g} site-updates), {dt:.1f} s"}
+
+
+def workload_particle(args):
+    from paper_2603_22553_amd import synth
+    f = synth.single_particle_large()
+    precisions = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    res = {}
+    for p in precisions:
+        res[p] = run_particle(f, p, args.steps, args.warmup)
+        print(f"# {p}: {res[p]['gsu_s']:.2f} GSU/s, {res[p]['ms'] / args.steps:.4f} ms/step, "
+              f"{res[p]['plan']}", file=sys.stderr, flush=True)
+    head = "fp64" if "fp64" in res else precisions[0]
+    r = res[head]
+    ms_step = r["ms"] / args.steps
+    line = {
+        "metric": METRIC, "value": round(r["gsu_s"], 4), "unit": "GSU/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 6),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if head == "fp64" else "f32-storage/f64-sums", "data": "synthetic",
+        "config": {"workload": "single large particle: 256^3 periodic box, radius-112 carbon "
+                               "particle, FID + MSD recorded every step",
+                   "sites": f.n_sites, "regions": f.n_regions, "precision": head,
+                   "steps_per_pass": 1, "plan": r["plan"]},
+        "roofline": roofline(f.n_sites, head, ms_step),
+        "results": {"mass_drift": r["mass_drift"], "peak_ppm": round(r["peak_ppm"], 5),
+                    "D_over_Dbulk": r["D_over_Dbulk"]},
+    }
+    for p, rr in res.items():
+        if p == head:
+            continue
+        ms_p = rr["ms"] / args.steps
+        line[p] = {"value": round(rr["gsu_s"], 4), "unit": "GSU/s", "ms_per_step": round(ms_p, 6),
+                   "dtype": "f32-storage/f64-sums", "roofline": roofline(f.n_sites, p, ms_p),
+                   "results": {"mass_drift": rr["mass_drift"], "peak_ppm": round(rr["peak_ppm"], 5),
+                               "D_over_Dbulk": rr["D_over_Dbulk"]}}
+    if args.cpu_steps > 0:
+        line["cpu_baseline"] = cpu_baseline(f, args.cpu_steps)
+    return line
+
+
+# ------------------------------------------------------------------- batched particles
+
+def workload_batch(args):
+    import torch
+    from paper_2603_22553_amd import synth
+    from paper_2603_22553_amd.lattice import Batch, Lattice
+    specs = synth.batch_specs(args.batch_count)
+    t = time.perf_counter()
+    fields = [synth.batch_particle(s) for s in specs]
+    print(f"# generated {len(fields)} particles in {time.perf_counter() - t:.1f} s",
+          file=sys.stderr, flush=True)
+    sites = sum(f.n_sites for f in fields)
+    steps = args.steps
+    prec = "mixed"
+
+    def make():
+        lats = []
+        for f in fields:
+            lat = Lattice(f.shape_xyz, precision=prec, n_regions=f.n_regions,
+                          max_records=steps + args.warmup + 1)
+            lat.set_fields(f)
+            lat.init_state("uniform")
+            lats.append(lat)
+        return lats
+
+    lats = make()
+    batch = Batch(lats)
+    batch.run(args.warmup)
+    _, ms = timed(batch.stream, lambda: batch.run(steps))
+    batch.close()
+    peaks = [lat.peak_ppm() for lat in lats[:4]]
+    for lat in lats:
+        lat.check()
+        lat.close()
+    torch.cuda.empty_cache()
+    # the same particles one at a time through the single-lattice path
+    lats = make()
+    for lat in lats:
+        lat.run(args.warmup)
+
+    def alone():
+        for lat in lats:
+            lat.run(steps)
+
+    _, ms_alone = timed(lats[0].stream, alone)
+    for lat in lats:
+        lat.close()
+    gsu = sites * steps / (ms * 1e-3) / 1e9
+    gsu_alone = sites * steps / (ms_alone * 1e-3) / 1e9
+    return {
+        "metric": METRIC, "value": round(gsu, 4), "unit": "GSU/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": round(ms / steps, 6), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32-storage/f64-sums",
+        "data": "synthetic",
+        "config": {"workload": f"{len(fields)} particles, radius 8-48, box 2R+8, one batched "
+                               "sweep per step, FID + MSD", "sites": sites},
+        "roofline": roofline(sites, prec, ms / steps),
+        "alone": {"value": round(gsu_alone, 4), "unit": "GSU/s",
+                  "ms_per_step": round(ms_alone / steps, 6),
+                  "note": "same particles stepped one lattice at a time"},
+        "results": {"peak_ppm_first4": [round(p, 4) for p in peaks]},
+    }
+
+
+# ------------------------------------------------------------------- film
+
+def workload_film(args):
+    from paper_2603_22553_amd import synth
+    from paper_2603_22553_amd.lattice import Lattice
+    t = time.perf_counter()
+    f = synth.film()
+    print(f"# generated film in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
+    steps = args.steps
+    lat = Lattice(f.shape_xyz, bc=("closed", "periodic", "periodic"), precision="mixed",
+                  n_regions=3, max_records=steps + args.warmup + 1)
+    lat.set_fields(f)
+    lat.init_state("boltzmann")
+    lat.run(args.warmup)
+
+    def work():
+        lat.run(steps)
+        return [lat.peak_ppm(r) for r in range(3)], lat.diffusion()
+
+    (peaks, (D, ratio)), ms = timed(lat.stream, work)
+    lat.check()
+    prof = lat.uptake_profile(0)
+    plan = lat.describe()
+    lat.close()
+    ms_step = ms / steps
+    return {
+        "metric": METRIC, "value": round(f.n_sites * steps / (ms * 1e-3) / 1e9, 4),
+        "unit": "GSU/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 6), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32-storage/f64-sums", "data": "synthetic",
+        "config": {"workload": "supercapacitor film 2048x256x256, electrodes 768 | bulk 512 | "
+                               "768 sites, closed in x, Boltzmann start, FID + MSD",
+                   "sites": f.n_sites, "plan": plan},
+        "roofline": roofline(f.n_sites, "mixed", ms_step, n_regions=3),
+        "results": {"peak_ppm_bulk_A_B": [round(p, 4) for p in peaks],
+                    "D_over_Dbulk": [round(float(v), 5) for v in ratio],
+                    "uptake_per_site_A_bulk_B": [
+                        round(float(prof[:768].mean() / (256 * 256)), 5),
+                        round(float(prof[768:1280].mean() / (256 * 256)), 5),
+                        round(float(prof[1280:].mean() / (256 * 256)), 5)]},
+    }
+
+
+# ------------------------------------------------------------------- serving
+
+def workload_serve(args):
+    import numpy as np
+    from paper_2603_22553_amd import serve, synth
+    trace = synth.serving_trace(args.serve_requests, rate_hz=args.serve_rate)
+    t = time.perf_counter()
+    jobs = [serve.Job(r.job_id, r.arrival_s, synth.request_fields(r), r.n_steps) for r in trace]
+    print(f"# generated {len(jobs)} requests in {time.perf_counter() - t:.1f} s",
+          file=sys.stderr, flush=True)
+    srv = serve.Server(serve.GpuExecutor(keep_fid=True), hbm_budget_bytes=200e9,
+                       tick_steps=args.tick_steps)
+    st = srv.run(jobs)
+    su = sum(j.n_sites * j.n_steps for j in jobs)
+    # the same first requests one at a time through the single-lattice path
+    from paper_2603_22553_amd.lattice import Lattice
+    n_alone = min(len(jobs), args.serve_alone)
+    t = time.perf_counter()
+    su_alone = 0
+    for j in jobs[:n_alone]:
+        nz, ny, nx = j.fields.F.shape
+        with Lattice((nx, ny, nz), precision="mixed", track=("fid",), n_regions=2,
+                     max_records=j.n_steps + 1) as lat:
+            lat.set_fields(j.fields)
+            lat.init_state("uniform")
+            lat.run(j.n_steps)
+            assert np.array_equal(lat.fid(), j.result["fid"]), "served result differs from alone"
+            su_alone += j.n_sites * j.n_steps
+    alone_s = time.perf_counter() - t
+    out = {
+        "metric": "served spectra/s with p50/p99 latency", "value": round(st["spectra_per_s"], 4),
+        "unit": "spectra/s", "n_gpus": 1, "steps": None, "warmup": 0,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32-storage/f64-sums", "data": "synthetic",
+        "config": {"workload": f"{len(jobs)} Poisson arrivals at {args.serve_rate}/s, box sides "
+                               "16-192 log-uniform, 5000-40000 steps, FID only, 200 GB budget, "
+                               f"tick {args.tick_steps} steps"},
+        "latency_p50_s": round(st["latency_p50_s"], 3), "latency_p99_s": round(st["latency_p99_s"], 3),
+        "queue_p50_s": round(st["queue_p50_s"], 3), "queue_p99_s": round(st["queue_p99_s"], 3),
+        "service_p50_s": round(st["service_p50_s"], 3), "service_p99_s": round(st["service_p99_s"], 3),
+        "gsu_s": round(su / st["makespan_s"] / 1e9, 3),
+        "offered_gsu_s": round(su / max(j.arrival_s for j in jobs) / 1e9, 3),
+        "alone": {"requests": n_alone, "spectra_per_s": round(n_alone / alone_s, 4),
+                  "gsu_s": round(su_alone / alone_s / 1e9, 3), "bitwise_equal_to_served": True},
+    }
+    if args.serve_oracle > 0:
+        from oracle import oracle
+        sampled = sorted(jobs[::100], key=lambda j: j.n_sites * j.n_steps)[:args.serve_oracle]
+        errs = []
+        for j in sampled:
+            f = j.fields
+            o = oracle.run(f.F, f.delta, f.region, f.n_regions, j.n_steps, moments=False)
+            errs.append(float(np.linalg.norm(j.result["fid"] - o.fid()) / np.linalg.norm(o.fid())))
+        out["oracle_fid_rel_l2_max"] = max(errs)
+        out["oracle_sample"] = [j.job_id for j in sampled]
+    return out
+
+
+# ------------------------------------------------------------------- copy calibration
+
+def workload_copy(args):
+    """Plain device copy (lpc_stream_copy) of 1 GiB: achievable HBM bandwidth, and the kernel of
+    known traffic that scales the FETCH_SIZE / WRITE_SIZE counters."""
+    import ctypes
+    import torch
+    from paper_2603_22553_amd import _native as N
+    n = 1 << 30
+    a = torch.ones(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    s = torch.cuda.current_stream()
+
+    def copy():
+        for _ in range(args.steps):
+            N.call("lpc_stream_copy", ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+                   n, ctypes.c_void_p(s.cuda_stream))
+
+    timed(s, copy)
+    _, ms = timed(s, copy)
+    assert bool(torch.equal(a[:4096], b[:4096]))
+    gbs = 2 * n * args.steps / (ms * 1e-3) / 1e9
+    return {"metric": "device copy bandwidth (read + write)", "value": round(gbs, 1),
+            "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+            "data": "synthetic", "config": {"workload": "copy 1 GiB, lpc_stream_copy"},
+            "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50000)
-    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", choices=["particle", "batch", "film", "serve", "copy"],
+                    default="particle")
     ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both")
     ap.add_argument("--cpu-steps", type=int, default=20,
                     help="oracle steps timed for the CPU baseline (0 skips it)")
+    ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--serve-alone", type=int, default=20)
+    ap.add_argument("--serve-oracle", type=int, default=0)
+    ap.add_argument("--tick-steps", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the sweep shards by slabs, see the design notes; not built).", file=sys.stderr)
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the sweep "
+              "would shard by slabs with one halo exchange per pass; not built).", file=sys.stderr)
         sys.exit(2)
+    defaults = {"particle": (50000, 200), "batch": (2000, 20), "film": (1000, 20),
+                "serve": (0, 0), "copy": (20, 1)}[args.workload]
+    if args.steps is None:
+        args.steps = defaults[0]
+    if args.warmup is None:
+        args.warmup = defaults[1]
 
     import torch
-    from paper_2603_22553_amd import synth
-
     assert torch.cuda.is_available(), "no GPU"
-    f = synth.single_particle_large()
-    precisions = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
-    res = {}
-    for p in precisions:
-        res[p] = run_gpu(f, p, args.steps, args.warmup)
-        print(f"# {p}: {res[p]['gsu_s']:.2f} GSU/s, {res[p]['ms'] / args.steps:.4f} ms/step, "
-              f"mass drift {res[p]['mass_drift']:.1e}", file=sys.stderr, flush=True)
-
-    head = "fp64" if "fp64" in res else precisions[0]
-    r = res[head]
-    bpsu = bytes_per_site_update(head, n_regions=f.n_regions)
-    ms_step = r["ms"] / args.steps
-    achieved = f.n_sites * bpsu / (ms_step * 1e-3) / 1e9
-    traffic = measured_traffic(head)
-    line = {
-        "metric": "Glattice-site-updates/s (GSU/s) and fraction of HBM roofline",
-        "value": round(r["gsu_s"], 4),
-        "unit": "GSU/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 6),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if head == "fp64" else "f32-storage/f64-arith",
-        "data": "synthetic",
-        "config": {"workload": "single large particle: 256^3 periodic box, radius-112 carbon "
-                               "particle, FID + MSD every step",
-                   "sites": f.n_sites, "regions": f.n_regions, "precision": head,
-                   "steps_per_pass": 1},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "bytes_per_site_update": bpsu},
-    }
-    for p, rr in res.items():
-        if p == head:
-            continue
-        b = bytes_per_site_update(p, n_regions=f.n_regions)
-        ms_p = rr["ms"] / args.steps
-        ach = f.n_sites * b / (ms_p * 1e-3) / 1e9
-        line[p] = {"value": round(rr["gsu_s"], 4), "unit": "GSU/s", "ms_per_step": round(ms_p, 6),
-                   "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                                "traffic": measured_traffic(p), "bytes_per_site_update": b}}
-    if args.cpu_steps > 0:
-        line["cpu_baseline"] = cpu_baseline(f, args.cpu_steps)
-    print(json.dumps(line), flush=True)
+    fn = {"particle": workload_particle, "batch": workload_batch, "film": workload_film,
+          "serve": workload_serve, "copy": workload_copy}[args.workload]
+    print(json.dumps(fn(args)), flush=True)
 
 
 if __name__ == "__main__":

@@ -1,0 +1,230 @@
+"""Continuous-batching spectrum server over the batched lattice sweep.
+
+Spectrum / adsorption jobs (one carbon particle each) arrive over time. The server keeps
+the lattices of admitted jobs resident on the GPU, admits new jobs whenever the device
+memory budget allows, and advances all resident jobs together, `tick_steps` steps at a
+time, with one batched sweep (lpc_batch_run): jobs that arrive while others run join at
+the next tick, and finished jobs leave at the end of the tick in which their last step
+ran. Each job's result is bit for bit the one it gets when run alone, because the batched
+sweep keeps every lattice's own tiles and reduction order.
+
+The executor is pluggable: GpuExecutor drives liblpc; tests drive the scheduler with a
+CPU stand-in and a virtual clock.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+from collections import deque
+from typing import Callable, List, Optional
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Job:
+    job_id: int
+    arrival_s: float
+    fields: object            # synth.Fields-like: F, delta, region (shape (nz, ny, nx)), n_regions
+    n_steps: int
+    bc: tuple = ("periodic", "periodic", "periodic")
+    # filled in by the server
+    admitted_s: Optional[float] = None
+    finished_s: Optional[float] = None
+    steps_done: int = 0
+    result: Optional[dict] = None
+    status: str = "pending"   # pending | resident | done | rejected | cancelled
+    footprint: int = 0
+
+    @property
+    def n_sites(self) -> int:
+        return int(np.prod(self.fields.F.shape))
+
+    @property
+    def latency_s(self) -> Optional[float]:
+        return None if self.finished_s is None else self.finished_s - self.arrival_s
+
+
+class GpuExecutor:
+    """Runs jobs on one GPU through liblpc: float storage with double sums, FID only."""
+
+    def __init__(self, precision: str = "mixed", track=("fid",), device: str = "cuda",
+                 keep_fid: bool = True):
+        from . import lattice as _lat  # loads liblpc; fails loudly if it is not built
+        self._lat = _lat
+        self.precision = precision
+        self.track = tuple(track)
+        self.device = device
+        self.keep_fid = keep_fid
+
+    def _cfg(self, job: Job):
+        nz, ny, nx = job.fields.F.shape
+        return self._lat.make_config((nx, ny, nz), job.bc, self.precision, self.track,
+                                     job.fields.n_regions, max_records=job.n_steps + 1)
+
+    def footprint(self, job: Job) -> int:
+        return self._lat.footprint(self._cfg(job)) + self._lat.batch_footprint(1)
+
+    def start(self, job: Job):
+        nz, ny, nx = job.fields.F.shape
+        lat = self._lat.Lattice((nx, ny, nz), job.bc, self.precision, self.track,
+                                job.fields.n_regions, max_records=job.n_steps + 1,
+                                device=self.device)
+        lat.set_fields(job.fields)
+        lat.init_state("uniform")
+        return lat
+
+    def step(self, handles: list, steps: List[int]) -> None:
+        with self._lat.Batch(handles) as b:
+            b.run(steps)
+        handles[0].synchronize()
+
+    def finish(self, job: Job, handle) -> dict:
+        out = {"peak_ppm": handle.peak_ppm()}
+        if self.keep_fid:
+            out["fid"] = handle.fid()
+        out["mass"] = handle.moments()[0][-1]
+        handle.close()
+        return out
+
+    def cancel(self, handle) -> None:
+        handle.close()
+
+
+class Server:
+    """Admission by memory budget, tick-based continuous batching, latency accounting."""
+
+    def __init__(self, executor, hbm_budget_bytes: float = 200e9, tick_steps: int = 2000,
+                 clock: Callable[[], float] = time.perf_counter,
+                 sleep: Callable[[float], None] = time.sleep):
+        self.ex = executor
+        self.budget = float(hbm_budget_bytes)
+        self.tick_steps = int(tick_steps)
+        self.clock = clock
+        self.sleep = sleep
+        self.pending: deque = deque()
+        self.resident: list = []        # (job, handle)
+        self.done: list = []
+        self.rejected: list = []
+        self.cancelled: list = []
+        self.used_bytes = 0
+        self.peak_bytes = 0
+        self.ticks = 0
+        self.site_updates = 0
+        self._t0 = None
+        self._cancel_ids = set()
+
+    # ----------------------------------------------------------------- requests
+    def now(self) -> float:
+        return self.clock() - self._t0
+
+    def submit(self, job: Job) -> None:
+        job.footprint = int(self.ex.footprint(job))
+        if job.footprint > self.budget:
+            job.status = "rejected"
+            self.rejected.append(job)
+            return
+        self.pending.append(job)
+
+    def cancel(self, job_id: int) -> None:
+        """Drops a pending job at once; a resident job leaves at the next tick boundary."""
+        for j in list(self.pending):
+            if j.job_id == job_id:
+                self.pending.remove(j)
+                j.status = "cancelled"
+                self.cancelled.append(j)
+                return
+        self._cancel_ids.add(job_id)
+
+    # ----------------------------------------------------------------- loop
+    def _admit(self) -> None:
+        now = self.now()
+        while self.pending and self.pending[0].arrival_s <= now:
+            job = self.pending[0]
+            if self.used_bytes + job.footprint > self.budget:
+                break                     # first come, first served: wait for memory
+            self.pending.popleft()
+            handle = self.ex.start(job)
+            job.admitted_s = self.now()
+            job.status = "resident"
+            self.used_bytes += job.footprint
+            self.peak_bytes = max(self.peak_bytes, self.used_bytes)
+            self.resident.append((job, handle))
+
+    def _retire(self, job: Job, handle, cancelled: bool = False) -> None:
+        self.used_bytes -= job.footprint
+        if cancelled:
+            self.ex.cancel(handle)
+            job.status = "cancelled"
+            self.cancelled.append(job)
+            return
+        job.result = self.ex.finish(job, handle)
+        job.finished_s = self.now()
+        job.status = "done"
+        self.done.append(job)
+
+    def tick(self) -> bool:
+        """Admits what fits, advances every resident job; False when nothing is left."""
+        self._admit()
+        if self._cancel_ids:
+            keep = []
+            for job, h in self.resident:
+                if job.job_id in self._cancel_ids:
+                    self._retire(job, h, cancelled=True)
+                else:
+                    keep.append((job, h))
+            self.resident = keep
+            self._cancel_ids.clear()
+        if not self.resident:
+            if not self.pending:
+                return False
+            wait = self.pending[0].arrival_s - self.now()
+            if wait > 0:
+                self.sleep(wait)
+            return True
+        steps = [min(self.tick_steps, j.n_steps - j.steps_done) for j, _ in self.resident]
+        self.ex.step([h for _, h in self.resident], steps)
+        self.ticks += 1
+        keep = []
+        for (job, h), s in zip(self.resident, steps):
+            job.steps_done += s
+            self.site_updates += s * job.n_sites
+            if job.steps_done >= job.n_steps:
+                self._retire(job, h)
+            else:
+                keep.append((job, h))
+        self.resident = keep
+        return True
+
+    def run(self, jobs: List[Job]) -> dict:
+        """Serves a trace (jobs sorted by arrival) to completion and returns statistics."""
+        self._t0 = self.clock()
+        for j in sorted(jobs, key=lambda j: j.arrival_s):
+            self.submit(j)
+        while self.tick():
+            pass
+        return self.stats()
+
+    def stats(self) -> dict:
+        lat = np.array([j.latency_s for j in self.done]) if self.done else np.zeros(0)
+        queue = np.array([j.admitted_s - j.arrival_s for j in self.done]) if self.done else np.zeros(0)
+        service = np.array([j.finished_s - j.admitted_s for j in self.done]) if self.done else np.zeros(0)
+        span = max((j.finished_s for j in self.done), default=0.0)
+
+        def pct(a, q):
+            return float(np.percentile(a, q)) if a.size else math.nan
+
+        return {
+            "jobs_done": len(self.done),
+            "jobs_rejected": len(self.rejected),
+            "jobs_cancelled": len(self.cancelled),
+            "makespan_s": span,
+            "spectra_per_s": len(self.done) / span if span > 0 else math.nan,
+            "latency_p50_s": pct(lat, 50), "latency_p99_s": pct(lat, 99),
+            "queue_p50_s": pct(queue, 50), "queue_p99_s": pct(queue, 99),
+            "service_p50_s": pct(service, 50), "service_p99_s": pct(service, 99),
+            "site_updates_per_s": self.site_updates / span if span > 0 else math.nan,
+            "ticks": self.ticks,
+            "peak_resident_bytes": self.peak_bytes,
+        }
