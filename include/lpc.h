@@ -208,6 +208,13 @@ lpc_status lpc_batch_run(lpc_batch *batch, const int64_t *n_steps);
  * known traffic (bytes read + bytes written = 2 * bytes). Asynchronous. */
 lpc_status lpc_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
 
+/* Overrides the launch plan of the sweep: tile_x 64, 32 or 16 columns per tile row (0:
+ * the least padding in x) and zc planes per workgroup (0: chosen from the device's
+ * resident workgroups). Any plan computes the same step; the plan fixes the order of the
+ * per-step sums, so results are bitwise reproducible for a given plan and agree to
+ * rounding across plans. LPC_ERR_ARG if the plan's partial sums do not fit the arena. */
+lpc_status lpc_set_plan(lpc_lattice *lat, int32_t tile_x, int32_t zc);
+
 /* Launch plan of the sweep as text (tile shape, z-chunk, workgroups, steps finalised
  * together), NUL-terminated and truncated to cap bytes. */
 lpc_status lpc_describe(const lpc_lattice *lat, char *buf, size_t cap);

@@ -80,6 +80,7 @@ SIGNATURES = {
     "lpc_load_state": [_P, _P, _SZ],
     "lpc_stream_copy": [_P, _P, _SZ, _P],
     "lpc_describe": [_P, ctypes.c_char_p, _SZ],
+    "lpc_set_plan": [_P, _I32, _I32],
     "lpc_spectrum_length": [_P, _PI64],
     "lpc_spectrum": [_P, _I32, _I64, _P, _P, _P, _I64],
     "lpc_spectrum_peak": [_P, _I32, ctypes.POINTER(ctypes.c_double)],

@@ -198,6 +198,7 @@ struct lpc_lattice {
     bool initialized = false;
     int64_t steps_done = 0;
     double Fmin = 0.0;
+    int occupancy = 1, cus = 1;      // resident sweep workgroups per CU, compute units
 
     template <typename T = void>
     T *at(size_t off) const
@@ -428,6 +429,8 @@ lpc_status lpc_create(const lpc_config *cfg, void *arena, size_t arena_bytes, vo
     {
         lpc::Geometry g{cfg->n[0], cfg->n[1], cfg->n[2], {cfg->bc[0], cfg->bc[1], cfg->bc[2]}};
         const int occ = lpc::sweep_blocks_per_cu(cfg->precision, cfg->track, cfg->n_regions);
+        lat->occupancy = occ;
+        lat->cus = cus;
         lat->L.plan = lpc::make_plan(g, occ, cus, 0);
         set_chunk(lat->L);
     }
@@ -1292,6 +1295,41 @@ lpc_status lpc_stream_copy(const void *src, void *dst, size_t bytes, void *strea
     if (a < b + bytes && b < a + bytes)
         return fail(LPC_ERR_ARG, "buffers overlap");
     LPC_HIP(lpc::launch_stream_copy(src, dst, int64_t(bytes / 16), static_cast<hipStream_t>(stream)));
+    return ok();
+}
+
+lpc_status lpc_set_plan(lpc_lattice *lat, int32_t tile_x, int32_t zc)
+{
+    if (!lat)
+        return fail(LPC_ERR_ARG, "lattice is NULL");
+    if (tile_x != 0 && tile_x != 64 && tile_x != 32 && tile_x != 16)
+        return fail(LPC_ERR_ARG, "tile_x = %d is not 0, 64, 32 or 16", tile_x);
+    if (zc < 0)
+        return fail(LPC_ERR_ARG, "zc = %d is negative", zc);
+    if (lpc_status s = use_device(lat))
+        return s;
+    lpc::Geometry g{lat->cfg.n[0], lat->cfg.n[1], lat->cfg.n[2],
+                    {lat->cfg.bc[0], lat->cfg.bc[1], lat->cfg.bc[2]}};
+    lpc::SweepPlan p = lpc::make_plan(g, lat->occupancy, lat->cus, tile_x);
+    if (zc > 0)
+        p = lpc::with_z_chunk(p, g, zc);
+    if (size_t(p.nblocks) * lat->L.K * 8 > lat->L.partial_bytes)
+        return fail(LPC_ERR_ARG, "plan with %lld workgroups does not fit the partial sums",
+                    (long long)p.nblocks);
+    if (lpc_status s = sync(lat))
+        return s;
+    Layout L = lat->L;
+    L.plan = p;
+    set_chunk(L);
+    SoloTables tables{};
+    lat->L = L;
+    tables.item = lat->sweep_item(0);
+    tables.prefix[0] = 0;
+    tables.prefix[1] = p.nblocks;
+    tables.fin = lat->finalize_item(0);
+    tables.kprefix[0] = 0;
+    tables.kprefix[1] = L.K;
+    LPC_HIP(hipMemcpy(lat->solo(), &tables, sizeof tables, hipMemcpyHostToDevice));
     return ok();
 }
 

@@ -50,6 +50,8 @@ int64_t max_sweep_blocks(const Geometry &g);
 // Plan for g given the resident sweep workgroups per compute unit and the compute units;
 // tile_x 64, 32 or 16 fixes the tile width, anything else picks the least x padding.
 SweepPlan make_plan(const Geometry &g, int32_t blocks_per_cu, int32_t cus, int32_t tile_x);
+// The plan with its z-chunk forced to zc planes (zc >= 1).
+SweepPlan with_z_chunk(SweepPlan p, const Geometry &g, int32_t zc);
 // Resident sweep workgroups per compute unit for this precision, track set and regions.
 int sweep_blocks_per_cu(int32_t precision, uint32_t track, int32_t R);
 

@@ -923,12 +923,16 @@ SweepPlan make_plan(const Geometry &g, int32_t blocks_per_cu, int32_t cus, int32
     // Pick the z-chunk: every resident slot busy until the end (greedy makespan of the
     // chunks against the ideal), few extra planes per chunk (each chunk re-reads the two
     // planes around it, mostly from cache), and a few rounds to absorb uneven progress.
+    // A chunk of at least 4 planes (or the whole axis): shorter chunks re-read too large a
+    // share of planes around them, which costs more than the extra workgroups gain when the
+    // lattice shares the GPU with others.
+    const int32_t zc_min = std::min(g.nz, 4);
     double best = -1.0;
     int32_t best_zc = g.nz;
     for (int64_t gz = 1; gz <= gz_max; ++gz) {
         const int32_t zc = static_cast<int32_t>((g.nz + gz - 1) / gz);
         const int64_t gze = (g.nz + zc - 1) / zc;
-        if (gze != gz)
+        if (gze != gz || zc < zc_min)
             continue;
         const int64_t T = tiles * gze;
         const int64_t rounds = (T + conc - 1) / conc;
@@ -944,6 +948,14 @@ SweepPlan make_plan(const Geometry &g, int32_t blocks_per_cu, int32_t cus, int32
     p.zc = best_zc;
     p.gz = (g.nz + p.zc - 1) / p.zc;
     p.nblocks = tiles * p.gz;
+    return p;
+}
+
+SweepPlan with_z_chunk(SweepPlan p, const Geometry &g, int32_t zc)
+{
+    p.zc = std::max(1, std::min(zc, g.nz));
+    p.gz = (g.nz + p.zc - 1) / p.zc;
+    p.nblocks = static_cast<int64_t>(p.gx) * p.gy * p.gz;
     return p;
 }
 

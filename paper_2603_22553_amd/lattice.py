@@ -105,6 +105,19 @@ class Lattice:
     def __exit__(self, *exc):
         self.close()
 
+    def set_plan(self, tile_x: int = 0, zc: int = 0):
+        """Launch plan override: tile width 64/32/16 (0 automatic), z-chunk (0 automatic)."""
+        N.call("lpc_set_plan", self.handle, int(tile_x), int(zc))
+
+    @property
+    def plan(self) -> dict:
+        """The launch plan as a dict (tile, zc, workgroups)."""
+        import re
+        d = self.describe()
+        m = re.search(r"tile (\d+)x(\d+), zc (\d+), grid (\d+)x(\d+)x(\d+) = (\d+)", d)
+        tx, ty, zc, gx, gy, gz, nb = (int(v) for v in m.groups())
+        return {"tile_x": tx, "tile_y": ty, "zc": zc, "grid": (gx, gy, gz), "workgroups": nb}
+
     def describe(self) -> str:
         buf = ctypes.create_string_buffer(512)
         N.call("lpc_describe", self.handle, buf, len(buf))

@@ -167,3 +167,40 @@ def test_streams_and_async():
         lat.run(1000)
         rec = lat.records()
         assert rec.shape[0] == 1001 and np.all(np.isfinite(rec))
+
+
+def test_plan_override_and_autotune(tmp_path):
+    """Every plan computes the same step (FP64 records agree to rounding across plans and
+    are bitwise equal for a repeated plan); the autotuner picks one of its candidates and
+    caches it."""
+    from paper_2603_22553_amd import autotune
+    f = synth.random_fields((70, 20, 33), seed=21, n_regions=2)
+    recs = {}
+    for tx, zc in ((0, 0), (64, 5), (32, 1), (16, 33), (16, 4)):
+        with lattice(f.shape_xyz, n_regions=2, max_records=101) as lat:
+            lat.set_plan(tx, zc)
+            if tx:
+                assert lat.plan["tile_x"] == tx
+            if zc:
+                assert lat.plan["zc"] == zc
+            lat.set_fields(f)
+            lat.init_state()
+            lat.run(100)
+            recs[(tx, zc)] = lat.records()
+    ref = recs[(0, 0)]
+    for k, r in recs.items():
+        assert np.max(np.abs(r - ref)) <= 1e-12 * np.max(np.abs(ref)), k
+    with lattice(f.shape_xyz, n_regions=2, max_records=101) as lat:
+        lat.set_plan(32, 1)
+        lat.set_fields(f)
+        lat.init_state()
+        lat.run(100)
+        assert np.array_equal(lat.records(), recs[(32, 1)])
+        for bad in ((48, 0), (0, -1)):
+            with pytest.raises(N.LpcError) as e:
+                lat.set_plan(*bad)
+            assert e.value.status == N.LPC_ERR_ARG
+    cache = str(tmp_path / "tune.json")
+    tx, zc = autotune.tune((70, 20, 33), n_regions=2, steps=5, cache_path=cache)
+    assert (tx, zc) in autotune.candidates((70, 20, 33), zc) or tx in (64, 32, 16)
+    assert autotune.tune((70, 20, 33), n_regions=2, steps=5, cache_path=cache) == (tx, zc)
