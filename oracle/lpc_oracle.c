@@ -240,3 +240,61 @@ done:
     free(b.M2);
     return rc;
 }
+
+/*
+ * Equilibration phase (section 3.2, item "Equilibration process"): populations alone are
+ * stepped until they stop changing, max_i |rho_i(t+1) - rho_i(t)| <= tol * max_i rho_i(t+1),
+ * or until max_steps. rho holds the start and receives the result; *steps the number of steps
+ * taken and *residual the last relative change. Returns 0, 1 (bad argument) or 2 (memory).
+ */
+int lpc_oracle_equilibrate(int64_t nx, int64_t ny, int64_t nz, const int32_t *bc, double p0,
+                           const double *F, double *rho, double tol, int64_t max_steps,
+                           int64_t *steps, double *residual)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || !F || !rho || !steps || !residual || max_steps < 0)
+        return 1;
+    geometry g = {{nx, ny, nz}, {bc[0], bc[1], bc[2]}};
+    const int64_t n = nx * ny * nz;
+    double *zeros = calloc((size_t)n, sizeof(double));
+    double *ones = malloc(sizeof(double) * n);
+    double *b = malloc(sizeof(double) * n), *tmp_re = malloc(sizeof(double) * n),
+           *tmp_im = malloc(sizeof(double) * n), *re = calloc((size_t)n, sizeof(double)),
+           *im = calloc((size_t)n, sizeof(double));
+    if (!zeros || !ones || !b || !tmp_re || !tmp_im || !re || !im) {
+        free(zeros); free(ones); free(b); free(tmp_re); free(tmp_im); free(re); free(im);
+        return 2;
+    }
+    for (int64_t i = 0; i < n; ++i)
+        ones[i] = 1.0;
+    state cur = {rho, re, im, NULL, NULL}, nxt = {b, tmp_re, tmp_im, NULL, NULL};
+    double res = INFINITY;
+    int64_t t = 0;
+    while (t < max_steps) {
+        one_step(&g, p0, F, ones, zeros, &cur, &nxt);
+        ++t;
+        double dmax = 0.0, rmax = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            const double d = fabs(nxt.rho[i] - cur.rho[i]);
+            dmax = d > dmax ? d : dmax;
+            rmax = nxt.rho[i] > rmax ? nxt.rho[i] : rmax;
+        }
+        res = rmax > 0.0 ? dmax / rmax : 0.0;
+        state tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+        if (res <= tol)
+            break;
+    }
+    if (cur.rho != rho)
+        memcpy(rho, cur.rho, sizeof(double) * n);
+    *steps = t;
+    *residual = res;
+    free(zeros);
+    free(ones);
+    free(b);
+    free(tmp_re);
+    free(tmp_im);
+    free(re);
+    free(im);
+    return 0;
+}

@@ -51,6 +51,8 @@ def _load():
                                        i64, P]
         lib.lpc_oracle_run.restype = ctypes.c_int
         lib.lpc_oracle_threads.restype = ctypes.c_int
+        lib.lpc_oracle_equilibrate.argtypes = [i64, i64, i64, P, d, P, P, d, i64, P, P]
+        lib.lpc_oracle_equilibrate.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -141,6 +143,24 @@ def run(F, delta, region, n_regions, n_steps, bc=(PERIODIC, PERIODIC, PERIODIC),
     if rc != 0:
         raise RuntimeError(f"oracle failed with code {rc}")
     return Result(rec.reshape(n_steps + 1, K), n_regions, rho, re, im, M1, M2)
+
+
+def equilibrate(F, n_max, tol, bc=(PERIODIC, PERIODIC, PERIODIC), p0=1.0 / 7.0, rho=None):
+    """Equilibration phase: populations alone stepped until the largest change in one step,
+    relative to the largest population, is <= tol (or n_max steps). Returns
+    (rho, steps taken, last relative change)."""
+    lib = _load()
+    F = np.ascontiguousarray(F, dtype=np.float64)
+    nz, ny, nx = F.shape
+    r = np.ones(F.size) if rho is None else np.array(rho, dtype=np.float64, copy=True).reshape(-1)
+    steps = ctypes.c_int64()
+    res = ctypes.c_double()
+    bc_arr = np.asarray(bc, dtype=np.int32)
+    rc = lib.lpc_oracle_equilibrate(nx, ny, nz, _ptr(bc_arr), p0, _ptr(F), _ptr(r), tol, n_max,
+                                    ctypes.byref(steps), ctypes.byref(res))
+    if rc != 0:
+        raise RuntimeError(f"oracle equilibration failed with code {rc}")
+    return r.reshape(F.shape), int(steps.value), float(res.value)
 
 
 # ---------------------------------------------------------------- post-processing (Eq. (9))

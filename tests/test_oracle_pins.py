@@ -223,6 +223,53 @@ def test_einstein_equals_kohn(oracle):
         assert abs(res.msd()[tt, 0] - want) <= 1e-12 * want
 
 
+def test_vacf_from_msd_second_difference(oracle):
+    """Eq. (4): the second difference of the moment-propagated MSD from equilibrium gives
+    back the dense velocity autocorrelation (C(0) = MSD(1), C(tau) = half the second
+    difference); summed, it is the Kohn D of Eq. (4) truncated at the last lag."""
+    f = synth.random_fields((4, 4, 4), seed=37, F_scale=1.2)
+    t = 60
+    res = oracle.run(f.F, f.delta, f.region, 1, t, init="boltzmann", bc=(CLO, PER, PER))
+    rho_eq = _flat(oracle.boltzmann(f.F))
+    for a in range(3):
+        T0, T1, T2 = brute.matrices((4, 4, 4), (CLO, PER, PER), f.F, P0, axis=a)
+        C = brute.vacf(T0, T1, T2, rho_eq, t) / rho_eq.sum()
+        msd = res.msd()[:, a]
+        got = np.concatenate([[msd[1] - msd[0]], 0.5 * (msd[2:] - 2 * msd[1:-1] + msd[:-2])])
+        assert np.max(np.abs(got - C)) <= 1e-12 * C[0]
+
+
+# --------------------------------------------------------------------- P8a equilibration
+
+@pytest.mark.parametrize("bc", [(PER, PER, PER), (CLO, PER, CLO)])
+def test_equilibration_reaches_stationary_vector(oracle, bc):
+    """Equilibration phase (section 3.2): population steps alone until their one-step change
+    is below the threshold. The result is the eigenvector of the dense one-step matrix for
+    eigenvalue 1 (found by scipy's null space, not by stepping) and, by detailed balance,
+    the Boltzmann populations of Eq. (2)."""
+    import scipy.linalg
+    f = synth.random_fields((5, 4, 3), seed=41, F_scale=1.0)
+    rho, steps, res = oracle.equilibrate(f.F, 100000, 1e-13, bc=bc)
+    assert 0 < steps < 100000 and res <= 1e-13
+    assert abs(rho.sum() - f.n_sites) <= 1e-12 * f.n_sites           # mass kept
+    T0, _, _ = brute.matrices((5, 4, 3), bc, f.F, P0)
+    v = scipy.linalg.null_space(T0 - np.eye(f.n_sites))[:, 0]
+    v = v * f.n_sites / v.sum()
+    assert np.max(np.abs(_flat(rho) - v)) <= 1e-9 * v.max()
+    assert np.max(np.abs(_flat(rho) - _flat(oracle.boltzmann(f.F)))) <= 1e-9 * v.max()
+
+
+def test_equilibration_limits(oracle):
+    """The step cap is honoured, and a Boltzmann start is already converged at the first
+    check (its one-step change is rounding only)."""
+    f = synth.random_fields((6, 5, 4), seed=43)
+    rho, steps, res = oracle.equilibrate(f.F, 7, 0.0)
+    assert steps == 7 and res > 0
+    eq = oracle.boltzmann(f.F)
+    rho, steps, res = oracle.equilibrate(f.F, 1000, 1e-14, rho=eq)
+    assert steps == 1 and res <= 1e-14
+
+
 # --------------------------------------------------------------------- P8 no hopping
 
 def test_no_hop_limit(oracle):
