@@ -10,8 +10,9 @@ the device once at the end of the timed run. Inputs are resident in HBM before t
 
 Other workloads (--workload): `batch` (512 particles of radius 8-48 in one batched sweep,
 against the same particles run one at a time), `film` (2048 x 256 x 256 supercapacitor
-film, closed in x) and `serve` (Poisson arrivals of spectrum requests through the
-continuous-batching server). Each prints one JSON line.
+film, closed in x), `serve` (Poisson arrivals of spectrum requests through the
+continuous-batching server), `equilibrate` (the population-only equilibration phase on the
+256^3 particle) and `copy` (plain device copy). Each prints one JSON line.
 """
 from __future__ import annotations
 
@@ -272,6 +273,57 @@ def workload_film(args):
     }
 
 
+# ------------------------------------------------------------------- equilibration phase
+
+def workload_equilibrate(args):
+    """Equilibration phase on the 256^3 particle: populations alone, uniform start, a
+    one-step-change check every --check-every steps; the threshold is 0 so exactly --steps
+    steps run (the timed work does not depend on when a threshold would be met)."""
+    from paper_2603_22553_amd import synth
+    from paper_2603_22553_amd.lattice import Lattice
+    f = synth.single_particle_large()
+    precisions = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    res = {}
+    for p in precisions:
+        lat = Lattice(f.shape_xyz, precision=p, track=("fid", "msd"), n_regions=f.n_regions,
+                      max_records=2)
+        lat.set_fields(f)
+        lat.init_state("uniform")
+        lat.equilibrate(args.warmup, 0.0, args.check_every)
+        (steps, change), ms = timed(lat.stream,
+                                    lambda: lat.equilibrate(args.steps, 0.0, args.check_every))
+        assert steps == args.steps
+        mass = float(lat.population().sum())
+        lat.close()
+        res[p] = {"ms": ms, "gsu_s": f.n_sites * steps / (ms * 1e-3) / 1e9, "last_change": change,
+                  "mass_drift": abs(mass / f.n_sites - 1.0)}
+        print(f"# equilibrate {p}: {res[p]['gsu_s']:.2f} GSU/s", file=sys.stderr, flush=True)
+    head = "fp64" if "fp64" in res else precisions[0]
+    out = None
+    for p, r in res.items():
+        ms_step = r["ms"] / args.steps
+        rl = roofline(f.n_sites, p, ms_step, track=(), n_regions=f.n_regions)
+        rl["traffic"] = None
+        rl["check_bytes_per_site_update"] = round(16.0 / args.check_every, 3)
+        entry = {"value": round(r["gsu_s"], 4), "unit": "GSU/s", "ms_per_step": round(ms_step, 6),
+                 "dtype": "f64" if p == "fp64" else "f32-probabilities/f64-populations",
+                 "roofline": rl,
+                 "results": {"last_change": r["last_change"], "mass_drift": r["mass_drift"]}}
+        if p == head:
+            out = {"metric": METRIC, "value": entry["value"], "unit": "GSU/s", "n_gpus": 1,
+                   "steps": args.steps, "warmup": args.warmup, "ms_per_step": entry["ms_per_step"],
+                   "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                   "dtype": entry["dtype"], "data": "synthetic",
+                   "config": {"workload": "equilibration phase on the 256^3 radius-112 particle: "
+                                          "populations only, uniform start, change checked every "
+                                          f"{args.check_every} steps",
+                              "sites": f.n_sites, "precision": p},
+                   "roofline": rl, "results": entry["results"]}
+        else:
+            out[p] = entry
+    return out
+
+
 # ------------------------------------------------------------------- serving
 
 def workload_serve(args):
@@ -364,7 +416,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", choices=["particle", "batch", "film", "serve", "copy"],
+    ap.add_argument("--workload", choices=["particle", "batch", "film", "serve", "copy",
+                                           "equilibrate"],
                     default="particle")
     ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both")
     ap.add_argument("--cpu-steps", type=int, default=20,
@@ -375,13 +428,14 @@ def main():
     ap.add_argument("--serve-alone", type=int, default=20)
     ap.add_argument("--serve-oracle", type=int, default=0)
     ap.add_argument("--tick-steps", type=int, default=2000)
+    ap.add_argument("--check-every", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the sweep "
               "would shard by slabs with one halo exchange per pass; not built).", file=sys.stderr)
         sys.exit(2)
     defaults = {"particle": (50000, 200), "batch": (2000, 20), "film": (1000, 20),
-                "serve": (0, 0), "copy": (20, 1)}[args.workload]
+                "serve": (0, 0), "copy": (20, 1), "equilibrate": (5000, 200)}[args.workload]
     if args.steps is None:
         args.steps = defaults[0]
     if args.warmup is None:
@@ -390,7 +444,8 @@ def main():
     import torch
     assert torch.cuda.is_available(), "no GPU"
     fn = {"particle": workload_particle, "batch": workload_batch, "film": workload_film,
-          "serve": workload_serve, "copy": workload_copy}[args.workload]
+          "serve": workload_serve, "copy": workload_copy,
+          "equilibrate": workload_equilibrate}[args.workload]
     print(json.dumps(fn(args)), flush=True)
 
 

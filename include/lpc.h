@@ -117,6 +117,16 @@ lpc_status lpc_set_regions(lpc_lattice *lat, const uint8_t *region, int64_t n);
  * written. rho may be NULL unless mode is USER. */
 lpc_status lpc_init_state(lpc_lattice *lat, int32_t mode, const double *rho, int64_t n);
 
+/* Equilibration phase (section 3.2 of the paper): steps the populations alone, from the
+ * current state, until the largest change of one step relative to the largest population,
+ * max_i |rho_i(t+1) - rho_i(t)| / max_i rho_i(t+1), is <= tol, checked every check_every
+ * steps (>= 1), or until max_steps steps. Then restarts the propagation from the
+ * equilibrated populations: m = rho (real), M1 = M2 = 0, step counter 0, record row 0
+ * rewritten. *steps_taken (a multiple of check_every, or max_steps) and *residual (the
+ * last checked change) are optional. Synchronous. */
+lpc_status lpc_equilibrate(lpc_lattice *lat, int64_t max_steps, double tol, int64_t check_every,
+                           int64_t *steps_taken, double *residual);
+
 /* Queues n_steps steps. LPC_ERR_STATE if not initialised or if steps_done + n_steps
  * would exceed max_records - 1. */
 lpc_status lpc_run(lpc_lattice *lat, int64_t n_steps);
@@ -169,6 +179,16 @@ lpc_status lpc_spectrum_peak(lpc_lattice *lat, int32_t region, double *peak_ppm)
  * (2 (N - N/2) dt_s) in m^2/s, and ratio_a = D_a / D_bulk with D_bulk = p_hop a^2 / dt_s, the
  * free-lattice value. Needs LPC_TRACK_MSD and N >= 2; 3 values each. */
 lpc_status lpc_diffusion(lpc_lattice *lat, double *D_m2_s, double *ratio);
+
+/* Discrete velocity autocorrelation of Eq. (4) per axis, C(0) = <dx_1^2> and
+ * C(tau) = <dx_1 dx_{1+tau}>, for tau = 0..N-1, from the recorded mean-square displacement
+ * through the identity of a stationary increment process, MSD(t) = t C(0) +
+ * 2 sum_{tau=1}^{t-1} (t - tau) C(tau): C(0) = MSD(1) - MSD(0), C(tau) = (MSD(tau+1) -
+ * 2 MSD(tau) + MSD(tau-1)) / 2. Valid for runs started from equilibrium (Boltzmann start, or
+ * after lpc_equilibrate). The Kohn estimate of Eq. (4) truncated at lag T is then
+ * D_a(T) = a^2 [C(0)/2 + sum_{tau=1}^{T} C(tau)] / dt_s. Writes N rows of 3 values (lattice
+ * units^2); needs LPC_TRACK_MSD and N >= 2. */
+lpc_status lpc_read_vacf(lpc_lattice *lat, double *vacf_xyz, int64_t cap, int64_t *len);
 
 /* Populations of the current state summed over the planes perpendicular to `axis`
  * (0 x, 1 y, 2 z): n[axis] values (the uptake profile across a film along x). */

@@ -86,6 +86,8 @@ SIGNATURES = {
     "lpc_spectrum_peak": [_P, _I32, ctypes.POINTER(ctypes.c_double)],
     "lpc_diffusion": [_P, _P, _P],
     "lpc_uptake_profile": [_P, _I32, _P, _I64],
+    "lpc_equilibrate": [_P, _I64, ctypes.c_double, _I64, _PI64, ctypes.POINTER(ctypes.c_double)],
+    "lpc_read_vacf": [_P, _P, _I64, _PI64],
     "lpc_batch_query_footprint": [_I32, _PSZ],
     "lpc_batch_create": [_P, _I32, _P, _SZ, _P, ctypes.POINTER(_P)],
     "lpc_batch_destroy": [_P],

@@ -175,6 +175,46 @@ __global__ __launch_bounds__(kThreads) void k_profile(const double *rho, int nx,
     }
 }
 
+// Largest |a_i - b_i| and largest b_i over [0, n): per-workgroup maxima, then one pass.
+__global__ __launch_bounds__(kThreads) void k_change_partial(const double *a, const double *b,
+                                                             int64_t n, double *part)
+{
+    __shared__ double sd[kThreads], sb[kThreads];
+    double d = 0.0, m = 0.0;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kThreads) {
+        d = fmax(d, fabs(a[i] - b[i]));
+        m = fmax(m, b[i]);
+    }
+    sd[threadIdx.x] = d;
+    sb[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            sd[threadIdx.x] = fmax(sd[threadIdx.x], sd[threadIdx.x + s]);
+            sb[threadIdx.x] = fmax(sb[threadIdx.x], sb[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = sd[0];
+        part[2 * blockIdx.x + 1] = sb[0];
+    }
+}
+
+__global__ void k_change_final(const double *part, int nparts, double *out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0)
+        return;
+    double d = 0.0, m = 0.0;
+    for (int b = 0; b < nparts; ++b) {
+        d = fmax(d, part[2 * b]);
+        m = fmax(m, part[2 * b + 1]);
+    }
+    out[0] = d;
+    out[1] = m;
+}
+
 int grid_for(int64_t n)
 {
     int64_t g = (n + kThreads - 1) / kThreads;
@@ -207,6 +247,14 @@ hipError_t launch_argmax(const double *v, int64_t n, double *pval, int64_t *pidx
 {
     hipLaunchKernelGGL(k_argmax_partial, dim3(nparts), dim3(kThreads), 0, s, v, n, pval, pidx);
     hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(64), 0, s, pval, pidx, nparts, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_max_change(const double *prev, const double *next, int64_t n, double *part,
+                             int32_t nparts, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_change_partial, dim3(nparts), dim3(kThreads), 0, s, prev, next, n, part);
+    hipLaunchKernelGGL(k_change_final, dim3(1), dim3(64), 0, s, part, nparts, out);
     return hipGetLastError();
 }
 

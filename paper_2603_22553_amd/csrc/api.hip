@@ -613,6 +613,59 @@ lpc_status lpc_run(lpc_lattice *lat, int64_t n_steps)
     return ok();
 }
 
+lpc_status lpc_equilibrate(lpc_lattice *lat, int64_t max_steps, double tol, int64_t check_every,
+                           int64_t *steps_taken, double *residual)
+{
+    if (!lat)
+        return fail(LPC_ERR_ARG, "lattice is NULL");
+    if (max_steps < 0 || check_every < 1 || !std::isfinite(tol) || tol < 0.0)
+        return fail(LPC_ERR_ARG, "need max_steps >= 0, check_every >= 1, finite tol >= 0");
+    if (!lat->initialized)
+        return fail(LPC_ERR_STATE, "lpc_init_state or lpc_load_state must come first");
+    if (lpc_status s = use_device(lat))
+        return s;
+    SoloTables *t = lat->solo();
+    lpc::StepList list{&t->item, t->prefix, 1, lat->L.plan.tx, lat->L.plan.nblocks, 0, 0};
+    double *part = lat->at<double>(lat->L.off_argmax);     // kArgmaxParts x 2 doubles
+    double *out = lat->scalars() + 8;
+    int64_t done = 0;
+    double change[2] = {INFINITY, 1.0};
+    while (done < max_steps) {
+        const int64_t c = std::min(check_every, max_steps - done);
+        for (int64_t s = 0; s < c; ++s) {
+            list.parity = lat->cur;
+            LPC_HIP(lpc::launch_step_list(list, lat->cfg.precision, 0u, lat->cfg.n_regions,
+                                          lat->stream));
+            lat->cur ^= 1;
+        }
+        done += c;
+        LPC_HIP(lpc::launch_max_change(lat->st[1 - lat->cur].rho, lat->st[lat->cur].rho,
+                                       lat->L.n, part, kArgmaxParts, out, lat->stream));
+        if (lpc_status s = sync(lat))
+            return s;
+        LPC_HIP(hipMemcpy(change, out, 16, hipMemcpyDeviceToHost));
+        if (!std::isfinite(change[0]) || !std::isfinite(change[1]))
+            return fail(LPC_ERR_NONFINITE, "populations are not finite after %lld steps",
+                        (long long)done);
+        if (change[1] > 0.0 ? change[0] <= tol * change[1] : change[0] <= tol)
+            break;
+    }
+    // restart the propagation from the equilibrated populations
+    const lpc::StateView &st = lat->st[lat->cur];
+    LPC_HIP(lpc::launch_init_state(lat->cfg.precision, lat->cfg.track, st, st.rho, lat->L.n,
+                                   lat->stream));
+    lat->steps_done = 0;
+    if (lpc_status s = write_initial_record(lat))
+        return s;
+    if (lpc_status s = sync(lat))
+        return s;
+    if (steps_taken)
+        *steps_taken = done;
+    if (residual)
+        *residual = change[1] > 0.0 ? change[0] / change[1] : change[0];
+    return ok();
+}
+
 lpc_status lpc_synchronize(lpc_lattice *lat)
 {
     if (!lat)
@@ -1040,6 +1093,39 @@ lpc_status lpc_diffusion(lpc_lattice *lat, double *D_m2_s, double *ratio)
         D_m2_s[a] = a2 * slope / (2.0 * lat->cfg.dt_s);
         ratio[a] = lat->cfg.p_hop > 0.0 ? slope / (2.0 * lat->cfg.p_hop) : 0.0;
     }
+    return ok();
+}
+
+lpc_status lpc_read_vacf(lpc_lattice *lat, double *vacf_xyz, int64_t cap, int64_t *len)
+{
+    if (!lat || !vacf_xyz || !len)
+        return fail(LPC_ERR_ARG, "NULL argument");
+    if (!msd_of(lat->cfg))
+        return fail(LPC_ERR_STATE, "displacement moments are not tracked");
+    const int64_t N = lat->steps_done;
+    if (N < 2)
+        return fail(LPC_ERR_STATE, "the autocorrelation needs at least 2 steps");
+    if (cap < N)
+        return fail(LPC_ERR_OOM, "autocorrelation has %lld rows, buffer holds %lld", (long long)N,
+                    (long long)cap);
+    std::vector<double> rec;
+    if (lpc_status s = fetch_records(lat, rec))
+        return s;
+    if (lpc_status s = health(lat, rec))
+        return s;
+    const int K = lat->L.K, R = lat->cfg.n_regions;
+    auto msd = [&](int64_t t, int a) {
+        double m = 0.0;
+        for (int r = 0; r < R; ++r)
+            m += rec[size_t(t * K + 2 * R + r)];
+        return rec[size_t(t * K + 3 * R + 3 + a)] / m;
+    };
+    for (int a = 0; a < 3; ++a) {
+        vacf_xyz[a] = msd(1, a) - msd(0, a);
+        for (int64_t tau = 1; tau < N; ++tau)
+            vacf_xyz[3 * tau + a] = 0.5 * ((msd(tau + 1, a) - msd(tau, a)) - (msd(tau, a) - msd(tau - 1, a)));
+    }
+    *len = N;
     return ok();
 }
 

@@ -119,6 +119,10 @@ hipError_t launch_fid_spectrum(const double *records, int64_t rows, int32_t K, i
 // Index of the first maximum of v[0, n) into *out (nparts workgroup partials).
 hipError_t launch_argmax(const double *v, int64_t n, double *pval, int64_t *pidx, int32_t nparts,
                          int64_t *out, hipStream_t s);
+// out[0] = max_i |next_i - prev_i|, out[1] = max_i next_i (nparts workgroup partials of two
+// doubles in part).
+hipError_t launch_max_change(const double *prev, const double *next, int64_t n, double *part,
+                             int32_t nparts, double *out, hipStream_t s);
 // Population summed over the planes perpendicular to `axis`.
 hipError_t launch_profile(const double *rho, const Geometry &g, int32_t axis, double *profile,
                           hipStream_t s);

@@ -153,6 +153,16 @@ class Lattice:
         else:
             N.call("lpc_init_state", self.handle, INIT[mode], None, 0)
 
+    def equilibrate(self, max_steps: int, tol: float = 1e-12, check_every: int = 100):
+        """Equilibration phase: populations alone until their largest one-step change is
+        <= tol relative (checked every check_every steps); then the propagation restarts
+        from them (m = rho, moments 0, step 0). Returns (steps taken, last change)."""
+        steps = ctypes.c_int64()
+        res = ctypes.c_double()
+        N.call("lpc_equilibrate", self.handle, int(max_steps), float(tol), int(check_every),
+               ctypes.byref(steps), ctypes.byref(res))
+        return int(steps.value), float(res.value)
+
     # -------------------------------------------------------------- stepping
     def run(self, n_steps: int):
         N.call("lpc_run", self.handle, int(n_steps))
@@ -240,6 +250,21 @@ class Lattice:
         r = np.empty(3)
         N.call("lpc_diffusion", self.handle, _ptr(D), _ptr(r))
         return D, r
+
+    def vacf(self) -> np.ndarray:
+        """C(tau) = <dx_1 dx_{1+tau}> per axis, tau = 0..N-1 (Eq. (4)); runs from equilibrium."""
+        n = self.steps_done
+        out = np.empty((max(n, 1), 3))
+        got = ctypes.c_int64()
+        N.call("lpc_read_vacf", self.handle, _ptr(out), n, ctypes.byref(got))
+        return out[:got.value]
+
+    def kohn_diffusion(self, lag=None) -> np.ndarray:
+        """Eq. (4) truncated at `lag` (default: all recorded lags), m^2/s per axis."""
+        C = self.vacf()
+        T = C.shape[0] - 1 if lag is None else int(lag)
+        a2 = self.cfg.spacing_m ** 2
+        return a2 * (0.5 * C[0] + C[1:T + 1].sum(axis=0)) / self.cfg.dt_s
 
     def uptake_profile(self, axis=0) -> np.ndarray:
         n = self.shape_xyz[axis] if 0 <= axis < 3 else 1   # the library validates the axis
