@@ -23,7 +23,7 @@ import math
 import numpy as np
 import scipy.linalg
 
-PERIODIC, CLOSED = 0, 1
+PERIODIC, CLOSED, RESERVOIR = 0, 1, 2
 
 
 def _sites(shape_xyz):
@@ -35,7 +35,7 @@ def _sites(shape_xyz):
 
 
 def links(shape_xyz, bc):
-    """All directed links (source j, target i, hop vector) of the lattice."""
+    """All directed links (source j, target i, hop vector) between lattice sites."""
     nx, ny, nz = shape_xyz
     dims = (nx, ny, nz)
     out = []
@@ -45,7 +45,7 @@ def links(shape_xyz, bc):
                 c = [x, y, z]
                 c[axis] += sign
                 if not 0 <= c[axis] < dims[axis]:
-                    if bc[axis] == CLOSED:
+                    if bc[axis] != PERIODIC:
                         continue
                     c[axis] %= dims[axis]
                 i = c[0] + nx * (c[1] + ny * c[2])
@@ -55,23 +55,92 @@ def links(shape_xyz, bc):
     return out
 
 
-def matrices(shape_xyz, bc, F, p0, axis=0):
-    """T0, T1, T2 for displacement along `axis`; F flattened in x-fastest order."""
+def ghost_links(shape_xyz, bc):
+    """(site i, face f, hop vector ghost -> i) for every face site of a reservoir axis;
+    face f = 2 * axis + side, side 0 below coordinate 0 and 1 above n - 1."""
+    dims = tuple(shape_xyz)
+    out = []
+    for x, y, z, i in _sites(shape_xyz):
+        c = (x, y, z)
+        for axis in range(3):
+            if bc[axis] != RESERVOIR:
+                continue
+            for side, at, sign in ((0, 0, +1), (1, dims[axis] - 1, -1)):
+                if c[axis] == at:
+                    hop = [0, 0, 0]
+                    hop[axis] = sign
+                    out.append((i, 2 * axis + side, tuple(hop)))
+    return out
+
+
+def _acc(Ffrom, Fto):
+    """Eq. (1) written as a minimum; 0 into a site of infinite free energy."""
+    if math.isinf(Fto) and Fto > 0:
+        return 0.0
+    return min(1.0, math.exp(-(Fto - Ffrom)))
+
+
+def matrices(shape_xyz, bc, F, p0, axis=0, mobility=None, ghost=None):
+    """T0, T1, T2 for displacement along `axis`; F flattened in x-fastest order, +inf for
+    inaccessible sites (no row, no column). With `mobility` the link i-j is scaled by
+    min(mu_i, mu_j). With reservoir axes (ghost: 24 values, F, rho, Re m, Im m per face) it
+    also returns the per-step sources (s0, sm, s1, s2) that the ghost sites send in, so that
+    rho' = T0 rho + s0, m' = diag(e^{i theta}) (T0 m + sm), and so on."""
     F = np.asarray(F, dtype=np.float64).reshape(-1)
     n = F.size
+    mu = np.ones(n) if mobility is None else np.asarray(mobility, dtype=np.float64).reshape(-1)
+    open_ = ~(np.isinf(F) & (F > 0))
     T0 = np.zeros((n, n))
     T1 = np.zeros((n, n))
     T2 = np.zeros((n, n))
     leave = np.zeros(n)
     for j, i, hop in links(shape_xyz, bc):
-        p = p0 * min(1.0, math.exp(-(F[i] - F[j])))
+        if not (open_[i] and open_[j]):
+            continue
+        p = p0 * min(mu[i], mu[j]) * _acc(F[j], F[i])
         d = hop[axis]
         T0[i, j] += p
         T1[i, j] += p * d
         T2[i, j] += p * d * d
         leave[j] += p
-    T0[np.arange(n), np.arange(n)] += 1.0 - leave
-    return T0, T1, T2
+    s0 = np.zeros(n)
+    sm = np.zeros(n, dtype=np.complex128)
+    s1 = np.zeros(n)
+    s2 = np.zeros(n)
+    for i, f, hop in ghost_links(shape_xyz, bc):
+        if not open_[i]:
+            continue
+        Fg, rg, reg, img = ghost[4 * f:4 * f + 4]
+        a = min(mu[i], 1.0)
+        leave[i] += p0 * a * _acc(F[i], Fg)
+        p_in = p0 * a * _acc(Fg, F[i])
+        d = hop[axis]
+        s0[i] += p_in * rg
+        sm[i] += p_in * complex(reg, img)
+        s1[i] += p_in * d * rg
+        s2[i] += p_in * d * d * rg
+    T0[np.arange(n), np.arange(n)] += np.where(open_, 1.0 - leave, 0.0)
+    if ghost is None:
+        return T0, T1, T2
+    return T0, T1, T2, (s0, sm, s1, s2)
+
+
+def run_affine(T0, T1, T2, src, theta, rho0, m0, n_steps):
+    """Steps the dense affine system of a lattice with reservoir faces; returns per step the
+    sums of rho, m and the moments along the axis of T1/T2 (each from a zero start)."""
+    s0, sm, s1, s2 = src
+    A = np.exp(1j * theta)
+    rho = np.asarray(rho0, dtype=np.float64).copy()
+    m = np.asarray(m0, dtype=np.complex128).copy()
+    M1 = np.zeros_like(rho)
+    M2 = np.zeros_like(rho)
+    out = np.empty((n_steps + 1, 4), dtype=np.complex128)
+    out[0] = rho.sum(), m.sum(), 0.0, 0.0
+    for t in range(1, n_steps + 1):
+        rho, m, M1, M2 = (T0 @ rho + s0, A * (T0 @ m + sm), T0 @ M1 + T1 @ rho + s1,
+                          T0 @ M2 + 2.0 * (T1 @ M1) + T2 @ rho + s2)
+        out[t] = rho.sum(), m.sum(), M1.sum(), M2.sum()
+    return out
 
 
 def phases(delta_ppm, dt, nu0):

@@ -27,7 +27,20 @@
  *    then S1_x, S1_y, S1_z, S2_x, S2_y, S2_z.
  *
  * Boundaries: a periodic axis wraps the neighbour index (the hop vector stays +-1); a
- * closed axis has no neighbour beyond its faces.
+ * closed axis has no neighbour beyond its faces. A reservoir axis (Dirichlet ghost layer,
+ * section 3.2, item "Input reading and initialization") has beyond each face a ghost site
+ * whose values are fixed: free energy F_g, population rho_g, magnetisation m_g, zero
+ * displacement moments. Moves into the ghost leave the lattice; moves out of it bring
+ * p(g->i) times the ghost's values in. The lattice total is then not conserved.
+ *
+ * Inaccessible sites (section 2.1 and Fig. 1): a site whose free energy is +infinity is
+ * part of the solid matrix. It holds nothing, and a move attempted towards it is rejected
+ * (the particle stays), as is the zero acceptance into obstacles in Eq. (5).
+ *
+ * Link mobility (section 2.2, after Eq. (7)): with a per-site factor mu_i in [0, 1] the
+ * link i-j gets alpha_ij = min(mu_i, mu_j), the same for both directions so that detailed
+ * balance (and with it the Boltzmann equilibrium of Eq. (2)) is kept; both hop
+ * probabilities of the link are multiplied by it. A ghost site has mobility 1.
  *
  * Plain loops over z, y, x; OpenMP splits z-planes only. Record sums are taken per
  * z-plane in index order and then over planes in order, so results do not depend on
@@ -43,6 +56,7 @@
 
 #define ORACLE_PERIODIC 0
 #define ORACLE_CLOSED 1
+#define ORACLE_RESERVOIR 2
 
 static const int HOP[6][3] = {
     {+1, 0, 0}, {-1, 0, 0}, {0, +1, 0}, {0, -1, 0}, {0, 0, +1}, {0, 0, -1}};
@@ -60,7 +74,8 @@ typedef struct {
     int bc[3];
 } geometry;
 
-/* Index of the neighbour of (x, y, z) one hop along direction d, or -1 across a closed face. */
+/* Index of the neighbour of (x, y, z) one hop along direction d; -1 across a closed face;
+ * -2 - f across reservoir face f = 2 * axis + (0 low, 1 high). */
 static int64_t neighbour(const geometry *g, int64_t x, int64_t y, int64_t z, int d)
 {
     int64_t c[3] = {x + HOP[d][0], y + HOP[d][1], z + HOP[d][2]};
@@ -68,18 +83,29 @@ static int64_t neighbour(const geometry *g, int64_t x, int64_t y, int64_t z, int
         if (c[a] < 0 || c[a] >= g->n[a]) {
             if (g->bc[a] == ORACLE_CLOSED)
                 return -1;
+            if (g->bc[a] == ORACLE_RESERVOIR)
+                return -2 - (2 * a + (c[a] < 0 ? 0 : 1));
             c[a] = (c[a] + g->n[a]) % g->n[a];
         }
     }
     return c[0] + g->n[0] * (c[1] + g->n[1] * c[2]);
 }
 
+static int blocked(double F) { return isinf(F) && F > 0.0; }
+
+/* Site-independent extras of a run: per-site mobility (NULL: all 1) and the ghost values of
+ * the six faces, ghost[4 * f + k] with k = F, rho, Re m, Im m (NULL: no reservoir face). */
+typedef struct {
+    const double *mobility;
+    const double *ghost;
+} extras;
+
 typedef struct {
     double *rho, *re, *im, *M1, *M2; /* M1, M2: 3 blocks of n (axis-major) or NULL */
 } state;
 
 static void one_step(const geometry *g, double p0, const double *F, const double *cos_t,
-                     const double *sin_t, const state *s, state *o)
+                     const double *sin_t, const extras *ex, const state *s, state *o)
 {
     const int64_t nx = g->n[0], ny = g->n[1], nz = g->n[2];
     const int64_t n = nx * ny * nz;
@@ -89,25 +115,57 @@ static void one_step(const geometry *g, double p0, const double *F, const double
         for (int64_t y = 0; y < ny; ++y) {
             for (int64_t x = 0; x < nx; ++x) {
                 const int64_t i = x + nx * (y + ny * z);
+                if (blocked(F[i])) { /* solid matrix: holds nothing */
+                    o->rho[i] = o->re[i] = o->im[i] = 0.0;
+                    if (moments)
+                        for (int a = 0; a < 3; ++a)
+                            o->M1[a * n + i] = o->M2[a * n + i] = 0.0;
+                    continue;
+                }
                 double out = 0.0;
                 double in_rho = 0.0, in_re = 0.0, in_im = 0.0;
                 double in1[3] = {0.0, 0.0, 0.0}, in2[3] = {0.0, 0.0, 0.0};
                 for (int d = 0; d < 6; ++d) {
                     const int64_t j = neighbour(g, x, y, z, d);
-                    if (j < 0)
+                    if (j == -1)
                         continue; /* attempt across a closed face: the particle stays */
-                    const double p_out = p0 * acceptance(F[i], F[j]); /* i -> j */
-                    const double p_in = p0 * acceptance(F[j], F[i]);  /* j -> i */
+                    /* the neighbour's values: a lattice site or a fixed ghost site */
+                    double Fj, rj, rej, imj, alpha = 1.0;
+                    double m1j[3] = {0.0, 0.0, 0.0}, m2j[3] = {0.0, 0.0, 0.0};
+                    if (j >= 0) {
+                        Fj = F[j];
+                        if (blocked(Fj))
+                            continue; /* attempt towards an obstacle: the particle stays */
+                        rj = s->rho[j];
+                        rej = s->re[j];
+                        imj = s->im[j];
+                        if (moments)
+                            for (int a = 0; a < 3; ++a) {
+                                m1j[a] = s->M1[a * n + j];
+                                m2j[a] = s->M2[a * n + j];
+                            }
+                        if (ex->mobility)
+                            alpha = fmin(ex->mobility[i], ex->mobility[j]);
+                    } else {
+                        const double *gh = ex->ghost + 4 * (-2 - j);
+                        Fj = gh[0];
+                        rj = gh[1];
+                        rej = gh[2];
+                        imj = gh[3];
+                        if (ex->mobility)
+                            alpha = fmin(ex->mobility[i], 1.0);
+                    }
+                    const double p_out = p0 * alpha * acceptance(F[i], Fj); /* i -> j */
+                    const double p_in = p0 * alpha * acceptance(Fj, F[i]);  /* j -> i */
                     out += p_out;
-                    in_rho += p_in * s->rho[j];
-                    in_re += p_in * s->re[j];
-                    in_im += p_in * s->im[j];
+                    in_rho += p_in * rj;
+                    in_re += p_in * rej;
+                    in_im += p_in * imj;
                     if (moments) {
                         for (int a = 0; a < 3; ++a) {
                             const double da = -HOP[d][a]; /* the move j -> i goes against d */
-                            const double m1 = s->M1[a * n + j], m2 = s->M2[a * n + j];
-                            in1[a] += p_in * (m1 + da * s->rho[j]);
-                            in2[a] += p_in * (m2 + 2.0 * da * m1 + da * da * s->rho[j]);
+                            in1[a] += p_in * (m1j[a] + da * rj);
+                            in2[a] += p_in * (m2j[a] + 2.0 * da * m1j[a] + da * da * rj);
                         }
                     }
                 }
@@ -177,15 +235,29 @@ int lpc_oracle_threads(void)
  * (n_steps + 1) * (3 R + 6) doubles: the record of the initial state, then one per step.
  * Returns 0 on success, 1 on a bad argument, 2 when memory runs out.
  */
+static int bad_extras(const int32_t *bc, const double *ghost)
+{
+    for (int a = 0; a < 3; ++a) {
+        if (bc[a] < ORACLE_PERIODIC || bc[a] > ORACLE_RESERVOIR)
+            return 1;
+        if (bc[a] == ORACLE_RESERVOIR && !ghost)
+            return 1;
+    }
+    return 0;
+}
+
 int lpc_oracle_run(int64_t nx, int64_t ny, int64_t nz, const int32_t *bc, double p0,
                    double dt_s, double larmor_hz, const double *F, const double *delta_ppm,
-                   const uint8_t *region, int32_t n_regions, double *rho, double *re,
-                   double *im, double *M1, double *M2, int64_t n_steps, double *records)
+                   const uint8_t *region, int32_t n_regions, const double *mobility,
+                   const double *ghost, double *rho, double *re, double *im, double *M1,
+                   double *M2, int64_t n_steps, double *records)
 {
     if (nx < 1 || ny < 1 || nz < 1 || n_regions < 1 || n_steps < 0 || !F || !delta_ppm ||
-        !region || !rho || !re || !im || !records || ((M1 == NULL) != (M2 == NULL)))
+        !region || !rho || !re || !im || !records || ((M1 == NULL) != (M2 == NULL)) ||
+        bad_extras(bc, ghost))
         return 1;
     geometry g = {{nx, ny, nz}, {bc[0], bc[1], bc[2]}};
+    const extras ex = {mobility, ghost};
     const int64_t n = nx * ny * nz;
     const int K = 3 * n_regions + 6;
     const int moments = M1 != NULL;
@@ -214,7 +286,7 @@ int lpc_oracle_run(int64_t nx, int64_t ny, int64_t nz, const int32_t *bc, double
     record(&g, region, n_regions, &a, plane_buf, records);
     state *cur = &a, *nxt = &b;
     for (int64_t t = 1; t <= n_steps; ++t) {
-        one_step(&g, p0, F, cos_t, sin_t, cur, nxt);
+        one_step(&g, p0, F, cos_t, sin_t, &ex, cur, nxt);
         record(&g, region, n_regions, nxt, plane_buf, records + t * K);
         state *tmp = cur;
         cur = nxt;
@@ -248,12 +320,15 @@ done:
  * taken and *residual the last relative change. Returns 0, 1 (bad argument) or 2 (memory).
  */
 int lpc_oracle_equilibrate(int64_t nx, int64_t ny, int64_t nz, const int32_t *bc, double p0,
-                           const double *F, double *rho, double tol, int64_t max_steps,
-                           int64_t *steps, double *residual)
+                           const double *F, const double *mobility, const double *ghost,
+                           double *rho, double tol, int64_t max_steps, int64_t *steps,
+                           double *residual)
 {
-    if (nx < 1 || ny < 1 || nz < 1 || !F || !rho || !steps || !residual || max_steps < 0)
+    if (nx < 1 || ny < 1 || nz < 1 || !F || !rho || !steps || !residual || max_steps < 0 ||
+        bad_extras(bc, ghost))
         return 1;
     geometry g = {{nx, ny, nz}, {bc[0], bc[1], bc[2]}};
+    const extras ex = {mobility, ghost};
     const int64_t n = nx * ny * nz;
     double *zeros = calloc((size_t)n, sizeof(double));
     double *ones = malloc(sizeof(double) * n);
@@ -270,7 +345,7 @@ int lpc_oracle_equilibrate(int64_t nx, int64_t ny, int64_t nz, const int32_t *bc
     double res = INFINITY;
     int64_t t = 0;
     while (t < max_steps) {
-        one_step(&g, p0, F, ones, zeros, &cur, &nxt);
+        one_step(&g, p0, F, ones, zeros, &ex, &cur, &nxt);
         ++t;
         double dmax = 0.0, rmax = 0.0;
         for (int64_t i = 0; i < n; ++i) {

@@ -4,7 +4,9 @@ Only the tests, the entry point's smoke check and the benchmark's CPU-baseline l
 this module. It loads `liblpc_oracle.so`, built from `lpc_oracle.c` by `build()` with the
 host C compiler, and adds plain numpy post-processing of the per-step records:
 
-* Boltzmann populations, Eq. (2): rho_i = <rho> exp(-F_i) / sum_j exp(-F_j).
+* Boltzmann populations, Eq. (2): rho_i = <rho> exp(-F_i) / sum_j exp(-F_j), with the
+  total equal to the number of accessible sites (the total of the uniform start).
+* Inaccessible sites are those with F = +inf; every start holds nothing on them.
 * FID normalised by its first sample (Eq. (8) is an average over spins).
 * Spectrum, Eq. (9), by numpy's FFT (kernel exp(-2 pi i k n / L)) after zero-filling to
   the next power of two >= 8 (N+1) samples; peak by parabolic interpolation of Re F.
@@ -25,7 +27,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "lpc_oracle.c")
 LIB = os.path.join(HERE, "liblpc_oracle.so")
 
-PERIODIC, CLOSED = 0, 1
+PERIODIC, CLOSED, RESERVOIR = 0, 1, 2
 _lib = None
 
 
@@ -48,10 +50,10 @@ def _load():
         d, i64, i32 = ctypes.c_double, ctypes.c_int64, ctypes.c_int32
         P = ctypes.c_void_p
         lib.lpc_oracle_run.argtypes = [i64, i64, i64, P, d, d, d, P, P, P, i32, P, P, P, P, P,
-                                       i64, P]
+                                       P, P, i64, P]
         lib.lpc_oracle_run.restype = ctypes.c_int
         lib.lpc_oracle_threads.restype = ctypes.c_int
-        lib.lpc_oracle_equilibrate.argtypes = [i64, i64, i64, P, d, P, P, d, i64, P, P]
+        lib.lpc_oracle_equilibrate.argtypes = [i64, i64, i64, P, d, P, P, P, P, d, i64, P, P]
         lib.lpc_oracle_equilibrate.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -65,10 +67,29 @@ def record_width(n_regions: int) -> int:
     return 3 * n_regions + 6
 
 
+def accessible(F: np.ndarray) -> np.ndarray:
+    """Mask of the sites that are not part of the solid matrix (F < +inf)."""
+    return ~np.isposinf(np.asarray(F, dtype=np.float64))
+
+
 def boltzmann(F: np.ndarray, mean_density: float = 1.0) -> np.ndarray:
-    """Eq. (2) with <rho> = mean_density: the populations of the Boltzmann distribution."""
-    w = np.exp(-(F - F.min()))          # the common factor exp(F_min) cancels in the ratio
-    return mean_density * F.size * w / w.sum()
+    """Eq. (2) with <rho> = mean_density per accessible site: the populations of the
+    Boltzmann distribution (zero on inaccessible sites)."""
+    F = np.asarray(F, dtype=np.float64)
+    acc = accessible(F)
+    w = np.exp(-(F - F[acc].min()))     # the common factor exp(F_min) cancels in the ratio
+    return mean_density * acc.sum() * w / w.sum()
+
+
+def ghosts(reservoir=None) -> np.ndarray | None:
+    """Ghost values of the six faces, 4 per face (F, rho, Re m, Im m), face = 2 * axis + side
+    (side 0 = low, 1 = high). `reservoir` maps (axis, side) to a tuple of those four."""
+    if not reservoir:
+        return None
+    g = np.zeros(24)
+    for (axis, side), vals in reservoir.items():
+        g[4 * (2 * axis + side):4 * (2 * axis + side) + 4] = vals
+    return g
 
 
 def _ptr(a):
@@ -109,12 +130,16 @@ class Result:
 
 
 def run(F, delta, region, n_regions, n_steps, bc=(PERIODIC, PERIODIC, PERIODIC), p0=1.0 / 7.0,
-        dt=5e-6, nu0=400e6, init="uniform", moments=True, state=None) -> Result:
-    """Run the oracle. Arrays have shape (nz, ny, nx). init: 'uniform' (rho = m = 1),
-    'boltzmann' (Eq. (2), m = rho) or an array of populations (m = rho). `state` =
-    (rho, re, im, M1, M2) continues from a saved state instead."""
+        dt=5e-6, nu0=400e6, init="uniform", moments=True, state=None, mobility=None,
+        reservoir=None) -> Result:
+    """Run the oracle. Arrays have shape (nz, ny, nx). init: 'uniform' (rho = m = 1 on
+    accessible sites), 'boltzmann' (Eq. (2), m = rho) or an array of populations (m = rho;
+    zeroed on inaccessible sites). `state` = (rho, re, im, M1, M2) continues from a saved
+    state instead. `mobility`: per-site factor in [0, 1]; `reservoir`: {(axis, side): (F,
+    rho, Re m, Im m)} for axes whose boundary is RESERVOIR."""
     lib = _load()
     F = np.ascontiguousarray(F, dtype=np.float64)
+    acc = accessible(F).reshape(-1)
     delta = np.ascontiguousarray(delta, dtype=np.float64)
     region = np.ascontiguousarray(region, dtype=np.uint8)
     nz, ny, nx = F.shape
@@ -129,6 +154,7 @@ def run(F, delta, region, n_regions, n_steps, bc=(PERIODIC, PERIODIC, PERIODIC),
             rho = boltzmann(F).reshape(-1)
         else:
             rho = np.array(init, dtype=np.float64, copy=True).reshape(-1)
+        rho = np.where(acc, rho, 0.0)
         re = rho.copy()
         im = np.zeros(n)
         M1 = np.zeros(3 * n) if moments else None
@@ -137,15 +163,18 @@ def run(F, delta, region, n_regions, n_steps, bc=(PERIODIC, PERIODIC, PERIODIC),
     K = record_width(n_regions)
     rec = np.zeros((n_steps + 1) * K)
     bc_arr = np.asarray(bc, dtype=np.int32)
+    mob = None if mobility is None else np.ascontiguousarray(mobility, dtype=np.float64).reshape(-1)
+    gh = ghosts(reservoir)
     rc = lib.lpc_oracle_run(nx, ny, nz, _ptr(bc_arr), p0, dt, nu0, _ptr(F), _ptr(delta),
-                            _ptr(region), n_regions, _ptr(rho), _ptr(re), _ptr(im), _ptr(M1),
-                            _ptr(M2), n_steps, _ptr(rec))
+                            _ptr(region), n_regions, _ptr(mob), _ptr(gh), _ptr(rho), _ptr(re),
+                            _ptr(im), _ptr(M1), _ptr(M2), n_steps, _ptr(rec))
     if rc != 0:
         raise RuntimeError(f"oracle failed with code {rc}")
     return Result(rec.reshape(n_steps + 1, K), n_regions, rho, re, im, M1, M2)
 
 
-def equilibrate(F, n_max, tol, bc=(PERIODIC, PERIODIC, PERIODIC), p0=1.0 / 7.0, rho=None):
+def equilibrate(F, n_max, tol, bc=(PERIODIC, PERIODIC, PERIODIC), p0=1.0 / 7.0, rho=None,
+                mobility=None, reservoir=None):
     """Equilibration phase: populations alone stepped until the largest change in one step,
     relative to the largest population, is <= tol (or n_max steps). Returns
     (rho, steps taken, last relative change)."""
@@ -153,11 +182,14 @@ def equilibrate(F, n_max, tol, bc=(PERIODIC, PERIODIC, PERIODIC), p0=1.0 / 7.0, 
     F = np.ascontiguousarray(F, dtype=np.float64)
     nz, ny, nx = F.shape
     r = np.ones(F.size) if rho is None else np.array(rho, dtype=np.float64, copy=True).reshape(-1)
+    r = np.ascontiguousarray(np.where(accessible(F).reshape(-1), r, 0.0))
+    mob = None if mobility is None else np.ascontiguousarray(mobility, dtype=np.float64).reshape(-1)
+    gh = ghosts(reservoir)
     steps = ctypes.c_int64()
     res = ctypes.c_double()
     bc_arr = np.asarray(bc, dtype=np.int32)
-    rc = lib.lpc_oracle_equilibrate(nx, ny, nz, _ptr(bc_arr), p0, _ptr(F), _ptr(r), tol, n_max,
-                                    ctypes.byref(steps), ctypes.byref(res))
+    rc = lib.lpc_oracle_equilibrate(nx, ny, nz, _ptr(bc_arr), p0, _ptr(F), _ptr(mob), _ptr(gh),
+                                    _ptr(r), tol, n_max, ctypes.byref(steps), ctypes.byref(res))
     if rc != 0:
         raise RuntimeError(f"oracle equilibration failed with code {rc}")
     return r.reshape(F.shape), int(steps.value), float(res.value)

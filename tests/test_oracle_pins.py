@@ -378,3 +378,178 @@ def test_restart_is_bitwise(oracle):
     assert np.array_equal(full.records[30:], b.records)
     assert np.array_equal(full.rho, b.rho) and np.array_equal(full.im, b.im)
     assert np.array_equal(full.M2, b.M2)
+
+
+# --------------------------------------------------------------------- P10 obstacles, link
+# mobility, reservoir faces (section 2.1 and Fig. 1; after Eq. (7); section 3.2)
+
+INF = math.inf
+RES = 2
+
+
+def _obstacles(shape_zyx, frac, seed):
+    rng = np.random.default_rng(seed)
+    return rng.random(shape_zyx) < frac
+
+
+def test_enclosed_site_only_precesses(oracle):
+    """A single accessible site walled in by obstacles: every attempt is rejected (Fig. 1),
+    so its population stays and its magnetisation only precesses, G(n) = exp(i n theta)."""
+    f = synth.random_fields((3, 3, 3), seed=71, delta_scale=5.0)
+    F = np.full((3, 3, 3), INF)
+    F[1, 1, 1] = 0.3
+    n = 300
+    res = oracle.run(F, f.delta, f.region, 1, n)
+    theta = brute.phases(f.delta, DT, NU0)[13]
+    assert np.allclose(res.mass(), 1.0, rtol=0, atol=1e-15)
+    assert np.max(np.abs(res.fid() - np.exp(1j * theta * np.arange(n + 1)))) <= 1e-12
+    assert np.all(res.s2() == 0.0)
+
+
+def test_channel_is_one_dimensional(oracle):
+    """A straight periodic channel of accessible sites through the solid: free 1-D diffusion
+    along it (MSD_x = 2 p0 n, Eq. (7) with d = 1) and no spread across it."""
+    F = np.full((5, 5, 16), INF)
+    F[2, 2, :] = 0.0
+    z = np.zeros_like(F)
+    n = 400
+    res = oracle.run(F, z, z.astype(np.uint8), 1, n)
+    msd = res.msd()
+    assert np.allclose(msd[:, 0], 2 * P0 * np.arange(n + 1), rtol=1e-12, atol=1e-12)
+    assert np.all(msd[:, 1:] == 0.0)
+    assert np.allclose(res.mass(), 16.0, rtol=1e-14)
+
+
+def test_one_step_msd_with_obstacles_eq5(oracle):
+    """Eq. (5) with p_acc = 0 towards obstacles: from a uniform start on a flat landscape
+    the one-step <dx^2> is p0 times the accessible x-links per accessible site, counted
+    directly on the mask."""
+    mask = _obstacles((6, 7, 8), 0.3, 73)
+    F = np.where(mask, INF, 0.0)
+    z = np.zeros(F.shape)
+    res = oracle.run(F, z, z.astype(np.uint8), 1, 1, bc=(PER, CLO, PER))
+    open_ = ~mask
+    for a, ax in ((0, 2), (1, 1), (2, 0)):
+        links = 0
+        for sh in (+1, -1):
+            nb = np.roll(open_, -sh, axis=ax)
+            ok = open_ & nb
+            if a == 1:                     # closed y: no link across the faces
+                edge = np.zeros_like(ok)
+                if sh > 0:
+                    edge[:, -1, :] = True
+                else:
+                    edge[:, 0, :] = True
+                ok &= ~edge
+            links += ok.sum()
+        assert abs(res.msd()[1, a] - P0 * links / open_.sum()) <= 1e-15
+
+
+@pytest.mark.parametrize("bc", [(PER, PER, PER), (CLO, PER, CLO)])
+def test_obstacles_mobility_dense_brute_force(oracle, bc):
+    """Random obstacles, random free energies and random per-site mobility on 4^3: FID and
+    moments equal the dense matrices built link by link with alpha_ij = min(mu_i, mu_j)."""
+    f = synth.random_fields((4, 4, 4), seed=75, F_scale=1.2, delta_scale=6.0)
+    mask = _obstacles((4, 4, 4), 0.25, 75)
+    F = np.where(mask, INF, f.F)
+    mu = np.random.default_rng(76).uniform(0.2, 1.0, size=(4, 4, 4))
+    n = 60
+    res = oracle.run(F, f.delta, f.region, 1, n, bc=bc, mobility=mu)
+    theta = brute.phases(f.delta, DT, NU0)
+    m0 = (~mask).reshape(-1).astype(np.float64)
+    T0, _, _ = brute.matrices((4, 4, 4), bc, F, P0, mobility=mu)
+    assert rel_l2(res.fid(), brute.fid(T0, theta, m0, n)) <= 1e-12
+    for a in range(3):
+        T0a, T1a, T2a = brute.matrices((4, 4, 4), bc, F, P0, axis=a, mobility=mu)
+        mom = brute.moments(T0a, T1a, T2a, m0, n)
+        assert np.allclose(res.s1()[:, a], mom[:, 1], rtol=0, atol=1e-12)
+        assert np.allclose(res.s2()[:, a], mom[:, 2], rtol=1e-12, atol=1e-12)
+    assert np.all(res.rho[mask.reshape(-1)] == 0.0)
+
+
+def test_boltzmann_stationary_with_obstacles_and_mobility(oracle):
+    """Detailed balance survives a symmetric link factor (after Eq. (7)) and obstacles: one
+    step from Eq. (2) (zero on obstacles, normalised to the accessible sites) changes
+    nothing beyond rounding."""
+    f = synth.random_fields((9, 7, 6), seed=77, F_scale=1.5)
+    mask = _obstacles((6, 7, 9), 0.2, 77)
+    F = np.where(mask, INF, f.F)
+    mu = np.random.default_rng(78).uniform(0.05, 1.0, size=F.shape)
+    eq = oracle.boltzmann(F)
+    assert abs(eq.sum() - (~mask).sum()) <= 1e-12 * eq.sum()
+    res = oracle.run(F, f.delta, f.region, 1, 3, bc=(CLO, PER, CLO), init="boltzmann",
+                     mobility=mu)
+    assert np.max(np.abs(res.rho - eq.reshape(-1))) <= 1e-14 * eq.max()
+
+
+def test_uniform_mobility_scales_free_diffusion(oracle):
+    """Eq. (7): a uniform factor c on every link scales alpha, hence the free-lattice MSD
+    slope, to 2 p0 c per axis."""
+    z = np.zeros((6, 5, 7))
+    c = 0.37
+    res = oracle.run(z, z, z.astype(np.uint8), 1, 50, mobility=np.full(z.shape, c))
+    n = np.arange(51)
+    for a in range(3):
+        assert np.allclose(res.msd()[:, a], 2 * P0 * c * n, rtol=1e-12, atol=1e-13)
+
+
+def test_reservoir_equilibrium_closed_form(oracle):
+    """Reservoir faces at one chemical potential (rho_g = K exp(-F_g) on every face) fix
+    the equilibrium to rho_i = K exp(-F_i) by detailed balance across the ghost links;
+    the equilibration reaches it from an empty lattice."""
+    f = synth.random_fields((5, 4, 6), seed=79, F_scale=0.8)
+    K = 2.5
+    res_faces = {}
+    for axis in (0, 2):
+        for side in (0, 1):
+            Fg = 0.3 * (axis - 1) + 0.2 * side
+            res_faces[(axis, side)] = (Fg, K * math.exp(-Fg), 0.0, 0.0)
+    rho, steps, r = oracle.equilibrate(f.F, 200000, 1e-13, bc=(RES, PER, RES),
+                                       rho=np.zeros(f.F.shape), reservoir=res_faces)
+    assert r <= 1e-13
+    want = K * np.exp(-f.F)
+    assert np.max(np.abs(rho - want)) <= 1e-10 * want.max()
+
+
+def test_reservoir_chain_linear_profile(oracle):
+    """A flat 1-D chain of n sites between two reservoirs (rho_L, rho_R) carries a steady
+    current, and its steady state is the linear profile through the ghosts:
+    rho(z) = rho_L + (rho_R - rho_L) (z + 1) / (n + 1)."""
+    n = 9
+    F = np.zeros((n, 1, 1))
+    rl, rr = 3.0, 0.5
+    rho, steps, r = oracle.equilibrate(F, 400000, 1e-14, bc=(CLO, CLO, RES),
+                                       reservoir={(2, 0): (0.0, rl, 0.0, 0.0),
+                                                  (2, 1): (0.0, rr, 0.0, 0.0)})
+    want = rl + (rr - rl) * (np.arange(n) + 1) / (n + 1)
+    assert np.max(np.abs(rho.reshape(-1) - want)) <= 1e-11
+
+
+@pytest.mark.parametrize("bc", [(RES, PER, CLO), (PER, RES, RES)])
+def test_reservoir_dense_affine(oracle, bc):
+    """Reservoir faces with magnetised ghosts, obstacles and mobility: population, FID and
+    moments equal the dense affine system (ghost links as a source term)."""
+    f = synth.random_fields((4, 3, 3), seed=81, F_scale=1.0, delta_scale=4.0)
+    mask = _obstacles((3, 3, 4), 0.2, 81)
+    F = np.where(mask, INF, f.F)
+    mu = np.random.default_rng(82).uniform(0.3, 1.0, size=F.shape)
+    rng = np.random.default_rng(83)
+    faces = {}
+    for axis in range(3):
+        if bc[axis] == RES:
+            for side in (0, 1):
+                faces[(axis, side)] = (rng.normal(0, 1), rng.uniform(0.5, 2), rng.normal(),
+                                       rng.normal())
+    n = 40
+    res = oracle.run(F, f.delta, f.region, 1, n, bc=bc, mobility=mu, reservoir=faces)
+    gh = oracle.ghosts(faces)
+    theta = brute.phases(f.delta, DT, NU0)
+    rho0 = (~mask).reshape(-1).astype(np.float64)
+    for a in range(3):
+        T0, T1, T2, src = brute.matrices((4, 3, 3), bc, F, P0, axis=a, mobility=mu, ghost=gh)
+        out = brute.run_affine(T0, T1, T2, src, theta, rho0, rho0, n)
+        assert np.allclose(res.mass(), out[:, 0].real, rtol=1e-12, atol=0)
+        assert rel_l2(res.fid(), out[:, 1]) <= 1e-12
+        assert np.allclose(res.s1()[:, a], out[:, 2].real, rtol=0, atol=1e-11)
+        assert np.allclose(res.s2()[:, a], out[:, 3].real, rtol=1e-12, atol=1e-11)
+    assert abs(res.mass()[-1] - res.mass()[0]) > 1e-3          # the faces exchange matter
