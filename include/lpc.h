@@ -57,7 +57,17 @@ typedef enum lpc_status {
     LPC_ERR_CONSERVATION = 6  /* total population drifted beyond conservation_tol */
 } lpc_status;
 
-enum { LPC_BC_PERIODIC = 0, LPC_BC_CLOSED = 1 };
+/* Boundary per axis. PERIODIC wraps; CLOSED has no neighbour beyond the faces (attempts
+ * across them stay); RESERVOIR puts a ghost site with fixed values beyond each face (the
+ * Dirichlet ghost layers of section 3.2, set by lpc_set_reservoir): moves into it leave
+ * the lattice and moves out of it bring its population and magnetisation in, so the
+ * total is not conserved and the conservation check is off for such a lattice. */
+enum { LPC_BC_PERIODIC = 0, LPC_BC_CLOSED = 1, LPC_BC_RESERVOIR = 2 };
+
+/* Options. MOBILITY adds a per-site mobility field mu (lpc_set_mobility): both hop
+ * probabilities of the link i-j are scaled by alpha_ij = min(mu_i, mu_j), one factor for
+ * both directions as detailed balance requires (section 2.2, after Eq. (7)). */
+enum { LPC_OPT_MOBILITY = 1u };
 
 /* FP64: every field, state array and operation in double. MIXED: populations stored
  * and updated in double; free energy, phase, magnetisation and moments stored and
@@ -74,11 +84,11 @@ enum { LPC_INIT_UNIFORM = 0, LPC_INIT_BOLTZMANN = 1, LPC_INIT_USER = 2 };
 
 typedef struct lpc_config {
     int32_t n[3];             /* nx, ny, nz >= 1 */
-    int32_t bc[3];            /* LPC_BC_PERIODIC or LPC_BC_CLOSED, per axis */
+    int32_t bc[3];            /* LPC_BC_PERIODIC, LPC_BC_CLOSED or LPC_BC_RESERVOIR */
     int32_t precision;        /* LPC_PREC_FP64 or LPC_PREC_MIXED */
     uint32_t track;           /* LPC_TRACK_FID | LPC_TRACK_MSD (0 = populations only) */
     int32_t n_regions;        /* 1..LPC_MAX_REGIONS */
-    int32_t reserved;         /* must be 0 */
+    uint32_t options;         /* LPC_OPT_* bits (0: none) */
     double p_hop;             /* attempt probability per neighbour, 0 <= 6 p_hop <= 1 (1/7) */
     double dt_s;              /* time step in seconds (5e-6) */
     double larmor_hz;         /* spectrometer Larmor frequency (400e6) */
@@ -104,17 +114,31 @@ lpc_status lpc_create(const lpc_config *cfg, void *arena, size_t arena_bytes, vo
                       lpc_lattice **out);
 lpc_status lpc_destroy(lpc_lattice *lat);
 
-/* Site free energies in kT (Eq. (1)); n must be nx*ny*nz; NaN/Inf -> LPC_ERR_NONFINITE. */
+/* Site free energies in kT (Eq. (1)); n must be nx*ny*nz. F = +INFINITY marks an
+ * inaccessible site (solid matrix, section 2.1 and Fig. 1): it holds nothing and every
+ * move towards it is rejected. NaN or -Inf -> LPC_ERR_NONFINITE; a finite |F| above 1e30
+ * -> LPC_ERR_ARG. */
 lpc_status lpc_set_free_energy(lpc_lattice *lat, const double *F_kT, int64_t n);
+/* Per-site mobility mu in [0, 1] (n values; needs LPC_OPT_MOBILITY, else LPC_ERR_STATE;
+ * out of range -> LPC_ERR_ARG, NaN -> LPC_ERR_NONFINITE). Starts at 1 everywhere. */
+lpc_status lpc_set_mobility(lpc_lattice *lat, const double *mu, int64_t n);
+/* Ghost site beyond face `side` (0: below coordinate 0, 1: above n - 1) of a RESERVOIR
+ * axis: free energy F_kT (finite, |F| <= 1e30), population rho >= 0 and magnetisation
+ * (m_re, m_im); its displacement moments are zero and its mobility 1. Starts at F = 0,
+ * rho = m = 0 (an empty, absorbing reservoir). LPC_ERR_STATE if the axis is not a
+ * reservoir axis. Takes effect from the next queued step. */
+lpc_status lpc_set_reservoir(lpc_lattice *lat, int32_t axis, int32_t side, double F_kT,
+                             double rho, double m_re, double m_im);
 /* Site chemical shifts in ppm (Eq. (11) phase per step); NaN/Inf -> LPC_ERR_NONFINITE. */
 lpc_status lpc_set_shift(lpc_lattice *lat, const double *delta_ppm, int64_t n);
 /* Region id per site, each < n_regions, else LPC_ERR_ARG. */
 lpc_status lpc_set_regions(lpc_lattice *lat, const uint8_t *region, int64_t n);
 
-/* Initial state: UNIFORM rho = 1; BOLTZMANN rho_i = N exp(-F_i) / sum_j exp(-F_j)
- * (Eq. (2), mean density 1); USER rho from the host array (finite, n values). In every
- * mode m = rho (real), M1 = M2 = 0, the step counter is reset and record row 0 is
- * written. rho may be NULL unless mode is USER. */
+/* Initial state: UNIFORM rho = 1; BOLTZMANN rho_i = N_open exp(-F_i) / sum_j exp(-F_j)
+ * (Eq. (2), mean density 1 over the N_open accessible sites); USER rho from the host
+ * array (finite, n values). Inaccessible sites get rho = 0 in every mode. In every mode
+ * m = rho (real), M1 = M2 = 0, the step counter is reset and record row 0 is written. rho
+ * may be NULL unless mode is USER. */
 lpc_status lpc_init_state(lpc_lattice *lat, int32_t mode, const double *rho, int64_t n);
 
 /* Equilibration phase (section 3.2 of the paper): steps the populations alone, from the

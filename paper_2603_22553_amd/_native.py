@@ -16,7 +16,8 @@ LPC_OK, LPC_ERR_ARG, LPC_ERR_OOM, LPC_ERR_DEVICE, LPC_ERR_STATE, LPC_ERR_NONFINI
     LPC_ERR_CONSERVATION = range(7)
 STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_OOM", 3: "ERR_DEVICE", 4: "ERR_STATE",
                 5: "ERR_NONFINITE", 6: "ERR_CONSERVATION"}
-BC_PERIODIC, BC_CLOSED = 0, 1
+BC_PERIODIC, BC_CLOSED, BC_RESERVOIR = 0, 1, 2
+OPT_MOBILITY = 1
 PREC_FP64, PREC_MIXED = 0, 1
 TRACK_FID, TRACK_MSD = 1, 2
 INIT_UNIFORM, INIT_BOLTZMANN, INIT_USER = 0, 1, 2
@@ -30,7 +31,7 @@ class Config(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("track", ctypes.c_uint32),
         ("n_regions", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("options", ctypes.c_uint32),
         ("p_hop", ctypes.c_double),
         ("dt_s", ctypes.c_double),
         ("larmor_hz", ctypes.c_double),
@@ -64,6 +65,9 @@ SIGNATURES = {
     "lpc_set_free_energy": [_P, _P, _I64],
     "lpc_set_shift": [_P, _P, _I64],
     "lpc_set_regions": [_P, _P, _I64],
+    "lpc_set_mobility": [_P, _P, _I64],
+    "lpc_set_reservoir": [_P, _I32, _I32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                          ctypes.c_double],
     "lpc_init_state": [_P, _I32, _P, _I64],
     "lpc_run": [_P, _I64],
     "lpc_synchronize": [_P],

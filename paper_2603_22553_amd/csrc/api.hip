@@ -47,6 +47,8 @@ constexpr int64_t kStagingMax = int64_t(1) << 22;   // doubles per host<->device
 constexpr int64_t kPartialBudget = int64_t(32) << 20; // bytes of per-step partials per chunk
 constexpr int64_t kChunkMax = 256;                    // steps finalised together
 constexpr int kScalars = 64;
+constexpr int kGhostValues = 24;   // 6 faces x (F, rho, Re m, Im m)
+constexpr double kMaxFreeEnergy = 1e30;
 constexpr int kArgmaxParts = 256;
 
 // Smallest power of two >= 8 * samples: the default zero-filled FFT length.
@@ -70,9 +72,9 @@ struct Layout {
     lpc::SweepPlan plan{};
     int64_t chunk = 1;
     int64_t staging = 0;
-    size_t off_F = 0, off_theta = 0, off_region = 0, off_partials = 0, off_records = 0,
-           off_staging = 0, off_scalars = 0, off_fft = 0, off_argmax = 0, off_profile = 0,
-           off_list = 0;
+    size_t off_F = 0, off_theta = 0, off_region = 0, off_mu = 0, off_ghost = 0, off_partials = 0,
+           off_records = 0, off_staging = 0, off_scalars = 0, off_fft = 0, off_argmax = 0,
+           off_profile = 0, off_list = 0;
     int64_t fft_max = 0;
     size_t off_rho[2] = {0, 0}, off_re[2] = {0, 0}, off_im[2] = {0, 0};
     size_t off_m1[2][3] = {}, off_m2[2][3] = {};
@@ -96,6 +98,20 @@ bool msd_of(const lpc_config &c)
 {
     return (c.track & LPC_TRACK_MSD) != 0;
 }
+bool mobility_of(const lpc_config &c)
+{
+    return (c.options & LPC_OPT_MOBILITY) != 0;
+}
+bool reservoir_of(const lpc_config &c)
+{
+    return c.bc[0] == LPC_BC_RESERVOIR || c.bc[1] == LPC_BC_RESERVOIR ||
+           c.bc[2] == LPC_BC_RESERVOIR;
+}
+// Track bits plus the kernel variant bits of the configuration.
+uint32_t variant_of(const lpc_config &c)
+{
+    return c.track | (mobility_of(c) || reservoir_of(c) ? lpc::kVariantExtended : 0u);
+}
 
 lpc_status validate_config(const lpc_config *c)
 {
@@ -104,8 +120,10 @@ lpc_status validate_config(const lpc_config *c)
     for (int a = 0; a < 3; ++a) {
         if (c->n[a] < 1)
             return fail(LPC_ERR_ARG, "n[%d] = %d must be >= 1", a, c->n[a]);
-        if (c->bc[a] != LPC_BC_PERIODIC && c->bc[a] != LPC_BC_CLOSED)
-            return fail(LPC_ERR_ARG, "bc[%d] = %d is not PERIODIC or CLOSED", a, c->bc[a]);
+        if (c->bc[a] != LPC_BC_PERIODIC && c->bc[a] != LPC_BC_CLOSED &&
+            c->bc[a] != LPC_BC_RESERVOIR)
+            return fail(LPC_ERR_ARG, "bc[%d] = %d is not PERIODIC, CLOSED or RESERVOIR", a,
+                        c->bc[a]);
     }
     if (int64_t(c->n[0]) * c->n[1] > (int64_t(1) << 28))
         return fail(LPC_ERR_ARG, "nx * ny must not exceed 2^28 (one z-plane of doubles < 2 GiB)");
@@ -115,8 +133,8 @@ lpc_status validate_config(const lpc_config *c)
         return fail(LPC_ERR_ARG, "track bits 0x%x unknown", c->track);
     if (c->n_regions < 1 || c->n_regions > LPC_MAX_REGIONS)
         return fail(LPC_ERR_ARG, "n_regions = %d outside 1..%d", c->n_regions, LPC_MAX_REGIONS);
-    if (c->reserved != 0)
-        return fail(LPC_ERR_ARG, "reserved field must be 0");
+    if (c->options & ~uint32_t(LPC_OPT_MOBILITY))
+        return fail(LPC_ERR_ARG, "option bits 0x%x unknown", c->options);
     if (!std::isfinite(c->p_hop) || c->p_hop < 0.0 || 6.0 * c->p_hop > 1.0)
         return fail(LPC_ERR_ARG, "p_hop = %g must satisfy 0 <= 6 p_hop <= 1", c->p_hop);
     if (!std::isfinite(c->dt_s) || !std::isfinite(c->larmor_hz) || !std::isfinite(c->spacing_m) ||
@@ -161,6 +179,8 @@ Layout plan_layout(const lpc_config &c)
     L.off_F = take(ns);
     L.off_theta = take(fid_of(c) ? ns : 0);
     L.off_region = take(size_t(L.n));
+    L.off_mu = take(mobility_of(c) ? ns : 0);
+    L.off_ghost = take(kGhostValues * 8);
     for (int b = 0; b < 2; ++b) {
         L.off_rho[b] = take(size_t(L.n) * 8);
         L.off_re[b] = take(fid_of(c) ? ns : 0);
@@ -198,6 +218,8 @@ struct lpc_lattice {
     bool initialized = false;
     int64_t steps_done = 0;
     double Fmin = 0.0;
+    int64_t n_open = 0;                       // accessible sites (F < +inf)
+    double ghost[kGhostValues] = {};          // host copy of the reservoir ghost table
     int occupancy = 1, cus = 1;      // resident sweep workgroups per CU, compute units
 
     template <typename T = void>
@@ -236,13 +258,15 @@ struct lpc_lattice {
         lpc::StepArgs a{};
         a.g = {cfg.n[0], cfg.n[1], cfg.n[2], {cfg.bc[0], cfg.bc[1], cfg.bc[2]}};
         a.precision = cfg.precision;
-        a.track = cfg.track;
+        a.track = variant_of(cfg);
         a.R = cfg.n_regions;
         a.K = L.K;
         a.p0 = cfg.p_hop;
         a.F = at(L.off_F);
         a.theta = at(L.off_theta);
         a.region = at<uint8_t>(L.off_region);
+        a.mu = mobility_of(cfg) ? at(L.off_mu) : nullptr;
+        a.ghost = at<double>(L.off_ghost);
         a.src = st[src];
         a.dst = st[1 - src];
         a.partials = partials();
@@ -324,7 +348,8 @@ lpc_status health(const lpc_lattice *lat, const std::vector<double> &rec)
         if (!std::isfinite(mass))
             return fail(LPC_ERR_NONFINITE, "total population is not finite at step %lld",
                         (long long)t);
-        const double tol = lat->cfg.conservation_tol;
+        // reservoir faces exchange matter with the lattice: no conservation to check
+        const double tol = reservoir_of(lat->cfg) ? 0.0 : lat->cfg.conservation_tol;
         if (tol > 0.0 && m0 != 0.0 && std::fabs(mass - m0) > tol * std::fabs(m0))
             return fail(LPC_ERR_CONSERVATION,
                         "total population drifted by %.3e (relative) at step %lld, tolerance %.1e",
@@ -428,7 +453,7 @@ lpc_status lpc_create(const lpc_config *cfg, void *arena, size_t arena_bytes, vo
     }
     {
         lpc::Geometry g{cfg->n[0], cfg->n[1], cfg->n[2], {cfg->bc[0], cfg->bc[1], cfg->bc[2]}};
-        const int occ = lpc::sweep_blocks_per_cu(cfg->precision, cfg->track, cfg->n_regions);
+        const int occ = lpc::sweep_blocks_per_cu(cfg->precision, variant_of(*cfg), cfg->n_regions);
         lat->occupancy = occ;
         lat->cus = cus;
         lat->L.plan = lpc::make_plan(g, occ, cus, 0);
@@ -459,8 +484,14 @@ lpc_status lpc_create(const lpc_config *cfg, void *arena, size_t arena_bytes, vo
         e = hipMemsetAsync(lat->at(L.off_theta), 0, ns, lat->stream);
     if (e == hipSuccess)
         e = hipMemsetAsync(lat->at(L.off_region), 0, size_t(L.n), lat->stream);
+    if (e == hipSuccess && mobility_of(*cfg))
+        e = lpc::launch_fill_field(cfg->precision, lat->at(L.off_mu), L.n, 1.0, lat->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(lat->at(L.off_ghost), lat->ghost, sizeof lat->ghost,
+                           hipMemcpyHostToDevice, lat->stream);
     if (e == hipSuccess)
         e = hipStreamSynchronize(lat->stream);
+    lat->n_open = L.n;
     if (e != hipSuccess) {
         delete lat;
         return fail(LPC_ERR_DEVICE, "clearing fields failed: %s", hipGetErrorString(e));
@@ -484,17 +515,35 @@ lpc_status lpc_set_free_energy(lpc_lattice *lat, const double *F_kT, int64_t n)
         return fail(LPC_ERR_ARG, "lattice is NULL");
     if (lpc_status s = check_sites(lat, F_kT, n))
         return s;
+    // +inf marks the solid matrix: stored as a finite sentinel beyond every accepted value
+    const double blocked =
+        lat->cfg.precision == LPC_PREC_FP64 ? lpc::kBlockedF64 : lpc::kBlockedF32;
+    std::vector<double> host;
     double fmin = INFINITY;
+    int64_t open = 0;
     for (int64_t i = 0; i < n; ++i) {
-        if (!std::isfinite(F_kT[i]))
-            return fail(LPC_ERR_NONFINITE, "F[%lld] is not finite", (long long)i);
-        fmin = F_kT[i] < fmin ? F_kT[i] : fmin;
+        const double f = F_kT[i];
+        if (std::isinf(f) && f > 0.0) {
+            if (host.empty())
+                host.assign(F_kT, F_kT + n);
+            host[size_t(i)] = blocked;
+            continue;
+        }
+        if (!std::isfinite(f))
+            return fail(LPC_ERR_NONFINITE, "F[%lld] is NaN or -Inf", (long long)i);
+        if (std::fabs(f) > kMaxFreeEnergy)
+            return fail(LPC_ERR_ARG, "|F[%lld]| = %g exceeds %g kT", (long long)i, std::fabs(f),
+                        kMaxFreeEnergy);
+        fmin = f < fmin ? f : fmin;
+        ++open;
     }
     if (lpc_status s = use_device(lat))
         return s;
-    if (lpc_status s = upload_field(lat, F_kT, lat->at(lat->L.off_F), 1.0))
+    if (lpc_status s = upload_field(lat, host.empty() ? F_kT : host.data(),
+                                    lat->at(lat->L.off_F), 1.0))
         return s;
-    lat->Fmin = fmin;
+    lat->Fmin = open > 0 ? fmin : 0.0;
+    lat->n_open = open;
     return ok();
 }
 
@@ -533,6 +582,52 @@ lpc_status lpc_set_regions(lpc_lattice *lat, const uint8_t *region, int64_t n)
     return sync(lat);
 }
 
+lpc_status lpc_set_mobility(lpc_lattice *lat, const double *mu, int64_t n)
+{
+    if (!lat)
+        return fail(LPC_ERR_ARG, "lattice is NULL");
+    if (!mobility_of(lat->cfg))
+        return fail(LPC_ERR_STATE, "the lattice was created without LPC_OPT_MOBILITY");
+    if (lpc_status s = check_sites(lat, mu, n))
+        return s;
+    for (int64_t i = 0; i < n; ++i) {
+        if (std::isnan(mu[i]))
+            return fail(LPC_ERR_NONFINITE, "mu[%lld] is NaN", (long long)i);
+        if (!(mu[i] >= 0.0 && mu[i] <= 1.0))
+            return fail(LPC_ERR_ARG, "mu[%lld] = %g is outside [0, 1]", (long long)i, mu[i]);
+    }
+    if (lpc_status s = use_device(lat))
+        return s;
+    return upload_field(lat, mu, lat->at(lat->L.off_mu), 1.0);
+}
+
+lpc_status lpc_set_reservoir(lpc_lattice *lat, int32_t axis, int32_t side, double F_kT,
+                             double rho, double m_re, double m_im)
+{
+    if (!lat)
+        return fail(LPC_ERR_ARG, "lattice is NULL");
+    if (axis < 0 || axis > 2 || side < 0 || side > 1)
+        return fail(LPC_ERR_ARG, "axis %d / side %d out of range", axis, side);
+    if (lat->cfg.bc[axis] != LPC_BC_RESERVOIR)
+        return fail(LPC_ERR_STATE, "axis %d is not a reservoir axis", axis);
+    if (!std::isfinite(F_kT) || !std::isfinite(rho) || !std::isfinite(m_re) ||
+        !std::isfinite(m_im))
+        return fail(LPC_ERR_NONFINITE, "reservoir values must be finite");
+    if (std::fabs(F_kT) > kMaxFreeEnergy || rho < 0.0)
+        return fail(LPC_ERR_ARG, "need |F| <= %g kT and rho >= 0", kMaxFreeEnergy);
+    if (lpc_status s = use_device(lat))
+        return s;
+    double *g = lat->ghost + 4 * (2 * axis + side);
+    g[0] = F_kT;
+    g[1] = rho;
+    g[2] = m_re;
+    g[3] = m_im;
+    // stream-ordered after the queued steps; the host table outlives the copy (synchronised)
+    LPC_HIP(hipMemcpyAsync(lat->at(lat->L.off_ghost), lat->ghost, sizeof lat->ghost,
+                           hipMemcpyHostToDevice, lat->stream));
+    return sync(lat);
+}
+
 lpc_status lpc_init_state(lpc_lattice *lat, int32_t mode, const double *rho, int64_t n)
 {
     if (!lat)
@@ -553,21 +648,24 @@ lpc_status lpc_init_state(lpc_lattice *lat, int32_t mode, const double *rho, int
     lat->cur = 0;
     const lpc::StateView &st = lat->st[0];
     const int64_t N = lat->L.n;
-    if (mode == LPC_INIT_UNIFORM) {
-        LPC_HIP(lpc::launch_init_state(lat->cfg.precision, lat->cfg.track, st, nullptr, N,
+    const void *F = lat->at(lat->L.off_F);
+    if (mode == LPC_INIT_UNIFORM || (mode == LPC_INIT_BOLTZMANN && lat->n_open == 0)) {
+        LPC_HIP(lpc::launch_init_state(lat->cfg.precision, lat->cfg.track, st, nullptr, F, N,
                                        lat->stream));
     } else if (mode == LPC_INIT_BOLTZMANN) {
-        // Eq. (2): rho_i = N exp(-F_i) / sum_j exp(-F_j); weights relative to min F
+        // Eq. (2): rho_i = N_open exp(-F_i) / sum_j exp(-F_j); weights relative to min F
+        // (inaccessible sites weigh exp(-huge) = 0)
         int64_t nb = 0;
-        LPC_HIP(lpc::launch_boltzmann_weights(lat->cfg.precision, lat->at(lat->L.off_F), lat->Fmin,
-                                              st.rho, N, lat->partials(), &nb, lat->stream));
+        LPC_HIP(lpc::launch_boltzmann_weights(lat->cfg.precision, F, lat->Fmin, st.rho, N,
+                                              lat->partials(), &nb, lat->stream));
         LPC_HIP(lpc::launch_finalize(lat->partials(), nb, 1, 1, lat->scalars(), lat->stream));
-        LPC_HIP(lpc::launch_boltzmann_scale(st.rho, N, double(N), lat->scalars(), lat->stream));
-        LPC_HIP(lpc::launch_init_state(lat->cfg.precision, lat->cfg.track, st, st.rho, N,
+        LPC_HIP(lpc::launch_boltzmann_scale(st.rho, N, double(lat->n_open), lat->scalars(),
+                                            lat->stream));
+        LPC_HIP(lpc::launch_init_state(lat->cfg.precision, lat->cfg.track, st, st.rho, F, N,
                                        lat->stream));
     } else {
         LPC_HIP(hipMemcpyAsync(st.rho, rho, size_t(N) * 8, hipMemcpyHostToDevice, lat->stream));
-        LPC_HIP(lpc::launch_init_state(lat->cfg.precision, lat->cfg.track, st, st.rho, N,
+        LPC_HIP(lpc::launch_init_state(lat->cfg.precision, lat->cfg.track, st, st.rho, F, N,
                                        lat->stream));
     }
     lat->steps_done = 0;
@@ -601,7 +699,7 @@ lpc_status lpc_run(lpc_lattice *lat, int64_t n_steps)
         for (int64_t s = 0; s < c; ++s) {
             list.parity = lat->cur;
             list.slot = s;
-            LPC_HIP(lpc::launch_step_list(list, lat->cfg.precision, lat->cfg.track,
+            LPC_HIP(lpc::launch_step_list(list, lat->cfg.precision, variant_of(lat->cfg),
                                           lat->cfg.n_regions, lat->stream));
             lat->cur ^= 1;
         }
@@ -634,8 +732,10 @@ lpc_status lpc_equilibrate(lpc_lattice *lat, int64_t max_steps, double tol, int6
         const int64_t c = std::min(check_every, max_steps - done);
         for (int64_t s = 0; s < c; ++s) {
             list.parity = lat->cur;
-            LPC_HIP(lpc::launch_step_list(list, lat->cfg.precision, 0u, lat->cfg.n_regions,
-                                          lat->stream));
+            LPC_HIP(lpc::launch_step_list(list, lat->cfg.precision,
+                                          variant_of(lat->cfg) & ~uint32_t(LPC_TRACK_FID |
+                                                                          LPC_TRACK_MSD),
+                                          lat->cfg.n_regions, lat->stream));
             lat->cur ^= 1;
         }
         done += c;
@@ -652,7 +752,8 @@ lpc_status lpc_equilibrate(lpc_lattice *lat, int64_t max_steps, double tol, int6
     }
     // restart the propagation from the equilibrated populations
     const lpc::StateView &st = lat->st[lat->cur];
-    LPC_HIP(lpc::launch_init_state(lat->cfg.precision, lat->cfg.track, st, st.rho, lat->L.n,
+    LPC_HIP(lpc::launch_init_state(lat->cfg.precision, lat->cfg.track, st, st.rho,
+                                   lat->at(lat->L.off_F), lat->L.n,
                                    lat->stream));
     lat->steps_done = 0;
     if (lpc_status s = write_initial_record(lat))
@@ -1299,32 +1400,37 @@ lpc_status lpc_batch_run(lpc_batch *batch, const int64_t *n_steps)
         if (active.empty())
             break;
         const int64_t steps = phase_end - done;
-        // work tables of this phase: one list per tile width, then the finalisation list
+        // work tables of this phase: one list per tile width and kernel variant (each lattice
+        // runs the kernel it runs alone), then the finalisation list
         items.clear();
         prefix.clear();
         fin.clear();
         kprefix.assign(1, 0);
         struct Group {
             int32_t tile_x, first, n;
+            uint32_t variant;
             size_t prefix_at;
             int64_t total;
         };
         std::vector<Group> groups;
         int64_t chunk = kChunkMax;
-        for (int32_t tx : {64, 32, 16}) {
-            Group gr{tx, int32_t(items.size()), 0, prefix.size(), 0};
-            prefix.push_back(0);
-            for (int32_t l : active) {
-                lpc_lattice *lat = batch->lats[l];
-                if (lat->L.plan.tx != tx)
-                    continue;
-                items.push_back(lat->sweep_item(lat->cur));
-                gr.total += lat->L.plan.nblocks;
-                prefix.push_back(gr.total);
-                ++gr.n;
+        for (uint32_t ext : {0u, lpc::kVariantExtended}) {
+            for (int32_t tx : {64, 32, 16}) {
+                Group gr{tx, int32_t(items.size()), 0, ext, prefix.size(), 0};
+                prefix.push_back(0);
+                for (int32_t l : active) {
+                    lpc_lattice *lat = batch->lats[l];
+                    if (lat->L.plan.tx != tx ||
+                        (variant_of(lat->cfg) & lpc::kVariantExtended) != ext)
+                        continue;
+                    items.push_back(lat->sweep_item(lat->cur));
+                    gr.total += lat->L.plan.nblocks;
+                    prefix.push_back(gr.total);
+                    ++gr.n;
+                }
+                if (gr.n > 0)
+                    groups.push_back(gr);
             }
-            if (gr.n > 0)
-                groups.push_back(gr);
         }
         for (int32_t l : active) {
             lpc_lattice *lat = batch->lats[l];
@@ -1349,8 +1455,9 @@ lpc_status lpc_batch_run(lpc_batch *batch, const int64_t *n_steps)
                 for (const Group &gr : groups) {
                     lpc::StepList list{batch->items + gr.first, batch->prefix + gr.prefix_at,
                                        gr.n, gr.tile_x, gr.total, int32_t((s0 + s) & 1), s};
-                    LPC_HIP(lpc::launch_step_list(list, batch->precision, batch->track,
-                                                  batch->maxr, batch->stream));
+                    LPC_HIP(lpc::launch_step_list(list, batch->precision,
+                                                  batch->track | gr.variant, batch->maxr,
+                                                  batch->stream));
                 }
             }
             LPC_HIP(lpc::launch_finalize_list(batch->fin, batch->kprefix, int32_t(active.size()),
@@ -1439,7 +1546,7 @@ const char *lpc_last_error(void)
 
 const char *lpc_version(void)
 {
-    return "liblpc 0.1 (gfx950)";
+    return "liblpc 0.2 (gfx950)";
 }
 
 }  // extern "C"

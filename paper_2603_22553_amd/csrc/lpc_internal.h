@@ -31,16 +31,33 @@ struct SweepPlan {
     int64_t nblocks;
 };
 
+// Kernel variant bit carried next to the track bits: the lattice has a mobility field or
+// a reservoir axis, and runs the extended sweep variant.
+constexpr uint32_t kVariantExtended = 4u;
+
+// Geometry.bc value of an axis with fixed ghost sites beyond its faces.
+constexpr int32_t kBcReservoir = 2;
+
+// Stored free energy of an inaccessible site: finite, so that differences with it stay
+// finite (and the hop probabilities into and out of it exact zeros), and beyond any
+// accepted free energy (|F| <= 1e30); one value per storage precision.
+constexpr double kBlockedF64 = 1e300;
+constexpr double kBlockedF32 = 3e38;
+// A stored free energy at or above this marks an inaccessible site.
+constexpr double kBlockedTest = 1e36;
+
 struct StepArgs {
     Geometry g;
     int32_t precision;   // 0 FP64, 1 mixed
-    uint32_t track;
+    uint32_t track;      // LPC_TRACK_* bits | kVariantExtended
     int32_t R;           // regions
     int32_t K;           // record width
     double p0;
     const void *F;
     const void *theta;
     const uint8_t *region;
+    const void *mu;        // per-site mobility (storage type), or null
+    const double *ghost;   // 6 faces x (F, rho, Re m, Im m) for reservoir axes
     StateView src, dst;
     double *partials;    // [K][nblocks] for this step
 };
@@ -100,7 +117,10 @@ hipError_t launch_store_field(int32_t precision, const double *src, void *dst, i
                               double scale, hipStream_t s);
 // Initial state: mode 0 uniform, 1 rho from `rho_src` (device, double), with m = rho, moments 0.
 hipError_t launch_init_state(int32_t precision, uint32_t track, const StateView &st,
-                             const double *rho_src, int64_t n, hipStream_t s);
+                             const double *rho_src, const void *F, int64_t n, hipStream_t s);
+// dst[i] = value for i < n in the storage type.
+hipError_t launch_fill_field(int32_t precision, void *dst, int64_t n, double value,
+                             hipStream_t s);
 // Boltzmann weights w_i = exp(-(F_i - Fmin)) into w, block sums into partials[nb].
 hipError_t launch_boltzmann_weights(int32_t precision, const void *F, double Fmin, double *w,
                                     int64_t n, double *partials, int64_t *nb, hipStream_t s);

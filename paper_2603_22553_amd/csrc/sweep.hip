@@ -20,6 +20,12 @@
 //    where six floats add exactly, so stay(i) = 1 - P_out is exact and the update
 //    stay * x_i + sum is finished in double before the one rounding to float; every
 //    remaining rounding is unbiased.
+// Inaccessible sites (section 2.1, Fig. 1) carry a huge finite free energy, so the same
+// arithmetic gives exact zero hop probabilities towards them, and they hold nothing. The
+// extended kernel variant (EXT) adds link mobility, both probabilities of the link i-j
+// scaled by min(mu_i, mu_j), and reservoir axes, where the neighbour beyond a face is a
+// ghost cell of fixed values (F, rho, m, zero moments, mobility 1); lattices that use
+// neither run the plain variant, which carries none of their registers.
 // Magnetisation rotates after the gather by the destination's phase (Eq. (13)), applied
 // as m + m (cos t - 1) + i m sin t with cos t - 1 = -2 sin^2(t/2), which keeps |m| from
 // drifting when t is stored in float.
@@ -180,14 +186,16 @@ __device__ inline int64_t logical_block(int64_t b, int64_t padded)
 
 // ---------------------------------------------------------------------------- one site
 
-// Values of one site that its neighbours read: population, free energy, magnetisation
-// and displacement moments, in the storage type S (rho is always double).
-template <typename S, bool FID, bool MSD>
+// Values of one site that its neighbours read: population, free energy, magnetisation,
+// displacement moments and (extended variant) mobility, in the storage type S (rho is
+// always double).
+template <typename S, bool FID, bool MSD, bool EXT>
 struct Cell {
     double rho;
     S F;
     S re, im;
     S m1[3], m2[3];
+    S mu;
 };
 
 // Byte offsets of one column (or halo column) in the 8-byte, S-sized and 1-byte arrays.
@@ -196,12 +204,14 @@ struct Off {
 };
 
 // Loads the values of a site that its neighbours read.
-template <typename S, bool FID, bool MSD>
-__device__ inline void load_cell(Cell<S, FID, MSD> &c, const View<S> &v, const S *F, int64_t pz,
-                                 Off o)
+template <typename S, bool FID, bool MSD, bool EXT>
+__device__ inline void load_cell(Cell<S, FID, MSD, EXT> &c, const View<S> &v, const S *F,
+                                 const S *MU, int64_t pz, Off o)
 {
     c.rho = ld(v.rho + pz, o.b8);
     c.F = ld(F + pz, o.bs);
+    if (EXT)
+        c.mu = MU ? ld(MU + pz, o.bs) : S(1);
     if (FID) {
         c.re = ld(v.re + pz, o.bs);
         c.im = ld(v.im + pz, o.bs);
@@ -213,6 +223,27 @@ __device__ inline void load_cell(Cell<S, FID, MSD> &c, const View<S> &v, const S
             c.m2[b] = ld(v.m2[b] + pz, o.bs);
         }
     }
+}
+
+// The fixed ghost site beyond reservoir face `face` (2 * axis + side): free energy,
+// population and magnetisation from the table, zero moments, mobility 1.
+template <typename S, bool FID, bool MSD, bool EXT>
+__device__ inline void ghost_cell(Cell<S, FID, MSD, EXT> &c, const double *ghost, int face)
+{
+    const double *v = ghost + 4 * face;
+    c.F = static_cast<S>(v[0]);
+    c.rho = v[1];
+    if (FID) {
+        c.re = static_cast<S>(v[2]);
+        c.im = static_cast<S>(v[3]);
+    }
+    if (MSD) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            c.m1[b] = c.m2[b] = S(0);
+    }
+    if (EXT)
+        c.mu = S(1);
 }
 
 // Gather accumulators of one site: sum_j p(j->i) x_j per field, the population term
@@ -246,8 +277,8 @@ __device__ inline void link_pair(S Fi, S Fj, S p0, S &p_out, S &p_in)
 
 // Gathers the fields arriving over one link from neighbour `nb`, which lies one hop along
 // axis AX with sign SGN; the arriving move nb -> i has hop component d = -SGN.
-template <int AX, int SGN, typename S, bool FID, bool MSD>
-__device__ inline void gather(const Cell<S, FID, MSD> &nb, S p_in, Acc<S> &f)
+template <int AX, int SGN, typename S, bool FID, bool MSD, bool EXT>
+__device__ inline void gather(const Cell<S, FID, MSD, EXT> &nb, S p_in, Acc<S> &f)
 {
     if (FID) {
         f.re = fma(p_in, nb.re, f.re);
@@ -272,23 +303,33 @@ __device__ inline void gather(const Cell<S, FID, MSD> &nb, S p_in, Acc<S> &f)
     }
 }
 
-template <int AX, int SGN, bool FID, bool MSD>
-__device__ inline void add_link(const Cell<double, FID, MSD> &c, const Cell<double, FID, MSD> &nb,
-                                double p0, Acc<double> &f)
+// Attempt probability of the link: p0, scaled in the extended variant by the smaller
+// mobility of its two ends (the same value at both ends; exactly p0 without a mobility
+// field).
+template <typename S, bool FID, bool MSD, bool EXT>
+__device__ inline S link_p0(const Cell<S, FID, MSD, EXT> &c, const Cell<S, FID, MSD, EXT> &nb,
+                            S p0)
+{
+    return EXT ? p0 * fmin(c.mu, nb.mu) : p0;
+}
+
+template <int AX, int SGN, bool FID, bool MSD, bool EXT>
+__device__ inline void add_link(const Cell<double, FID, MSD, EXT> &c,
+                                const Cell<double, FID, MSD, EXT> &nb, double p0, Acc<double> &f)
 {
     double p_out, p_in;
-    link_pair(c.F, nb.F, p0, p_out, p_in);
+    link_pair(c.F, nb.F, link_p0(c, nb, p0), p_out, p_in);
     f.rho += exact_flux(p_in, nb.rho, p_out, c.rho);
     f.pout += p_out;
     gather<AX, SGN>(nb, p_in, f);
 }
 
-template <int AX, int SGN, bool FID, bool MSD>
-__device__ inline void add_link(const Cell<float, FID, MSD> &c, const Cell<float, FID, MSD> &nb,
-                                float p0, Acc<float> &f)
+template <int AX, int SGN, bool FID, bool MSD, bool EXT>
+__device__ inline void add_link(const Cell<float, FID, MSD, EXT> &c,
+                                const Cell<float, FID, MSD, EXT> &nb, float p0, Acc<float> &f)
 {
     float p_out, p_in;
-    link_pair(c.F, nb.F, p0, p_out, p_in);
+    link_pair(c.F, nb.F, link_p0(c, nb, p0), p_out, p_in);
     f.rho = fma(static_cast<double>(p_in), nb.rho, f.rho);
     f.pout += static_cast<double>(p_out);
     gather<AX, SGN>(nb, p_in, f);
@@ -325,8 +366,8 @@ __device__ inline void half_angle(float t, float &s, float &c)
 
 // New state of a site from its old values and gather sums; stores it and adds its record
 // contributions.
-template <typename S, bool FID, bool MSD, int MAXR>
-__device__ inline void finish_site(const Cell<S, FID, MSD> &c, const Acc<S> &f, S theta, int r,
+template <typename S, bool FID, bool MSD, bool EXT, int MAXR>
+__device__ inline void finish_site(const Cell<S, FID, MSD, EXT> &c, const Acc<S> &f, S theta, int r,
                                    const View<S> &dst, int64_t pz, Off o, RecAcc<MAXR> &acc)
 {
     const double stay = 1.0 - f.pout;
@@ -360,18 +401,21 @@ __device__ inline void finish_site(const Cell<S, FID, MSD> &c, const Acc<S> &f, 
 }
 
 // LDS image of one z-plane of a tile with a one-site halo in x and y, one array per field.
-template <typename S, bool FID, bool MSD, int NL>
+template <typename S, bool FID, bool MSD, bool EXT, int NL>
 struct TileLds {
     double rho[NL];
     S F[NL];
     S re[FID ? NL : 1], im[FID ? NL : 1];
     S m1[3][MSD ? NL : 1], m2[3][MSD ? NL : 1];
+    S mu[EXT ? NL : 1];
 
     template <typename C>
     __device__ void put(int s, const C &c)
     {
         rho[s] = c.rho;
         F[s] = c.F;
+        if (EXT)
+            mu[s] = c.mu;
         if (FID) {
             re[s] = c.re;
             im[s] = c.im;
@@ -390,6 +434,8 @@ struct TileLds {
     {
         c.rho = rho[s];
         c.F = F[s];
+        if (EXT)
+            c.mu = mu[s];
         if (FID) {
             c.re = re[s];
             c.im = im[s];
@@ -423,34 +469,31 @@ __device__ inline void tile_coords(const SweepPlan &p, int64_t blk, int &bx, int
 // halo site.
 struct TileThread {
     Off own, halo;
-    int li, hslot;
+    int li, hslot, hghost;   // hghost: reservoir face whose ghost fills the halo slot, or -1
     bool act, has_xm, has_xp, has_ym, has_yp;
 };
 
 // One z-plane of the tile: stage it in LDS buffer `L` (own site + halo site), wait for the
 // whole tile, prefetch plane z+2 (own column) into `nx2` and the halo of plane z+1 into
 // `halo`, then update every site of the plane from LDS (x, y) and registers (z).
-template <typename S, bool FID, bool MSD, int MAXR, int TX, typename LDS>
+template <typename S, bool FID, bool MSD, bool EXT, int MAXR, int TX, typename LDS>
 __device__ __forceinline__ void plane_step(LDS &L, const StepArgs &a, const TileThread &th,
                                            const View<S> &src, const View<S> &dst, const S *F,
-                                           const S *TH, int64_t plane, int z, int z1,
-                                           const Cell<S, FID, MSD> &prv,
-                                           const Cell<S, FID, MSD> &cur,
-                                           const Cell<S, FID, MSD> &nxt,
-                                           Cell<S, FID, MSD> &nx2, Cell<S, FID, MSD> &halo,
-                                           RecAcc<MAXR> &acc)
+                                           const S *MU, const S *TH, int64_t plane, int z,
+                                           int z1, const Cell<S, FID, MSD, EXT> &prv,
+                                           const Cell<S, FID, MSD, EXT> &cur,
+                                           const Cell<S, FID, MSD, EXT> &nxt,
+                                           Cell<S, FID, MSD, EXT> &nx2,
+                                           Cell<S, FID, MSD, EXT> &halo, RecAcc<MAXR> &acc)
 {
     constexpr int COLS = TX + 2;
     const Geometry &g = a.g;
-    const bool zper = g.bc[2] == 0;
+    const bool zper = g.bc[2] == 0, zres = EXT && g.bc[2] == kBcReservoir;
     if (th.act)
         L.put(th.li, cur);
     if (th.hslot >= 0)
         L.put(th.hslot, halo);
     __syncthreads();
-    // The column offsets are re-materialised every plane so that base + offset is not
-    // hoisted into per-array 64-bit vector registers: each load then takes the plane's
-    // scalar base plus one 32-bit vector offset.
     // The column offsets are re-materialised every plane so that base + offset is not
     // hoisted into per-array 64-bit vector registers: each load then takes the plane's
     // scalar base plus one 32-bit vector offset.
@@ -460,15 +503,15 @@ __device__ __forceinline__ void plane_step(LDS &L, const StepArgs &a, const Tile
         // z + 2 <= nz here, so a periodic wrap lands on plane 0
         const int zn = z + 2 < g.nz ? z + 2 : (zper ? 0 : -1);
         if (th.act && zn >= 0)
-            load_cell(nx2, src, F, plane * zn, own);
-        if (th.hslot >= 0)
-            load_cell(halo, src, F, plane * (z + 1), hal);
+            load_cell(nx2, src, F, MU, plane * zn, own);
+        if (th.hslot >= 0 && (!EXT || th.hghost < 0))
+            load_cell(halo, src, F, MU, plane * (z + 1), hal);
     }
     if (!th.act)
         return;
     const S p0 = static_cast<S>(a.p0);
     Acc<S> f{};
-    Cell<S, FID, MSD> nb;
+    Cell<S, FID, MSD, EXT> nb;
     if (th.has_xm) {
         L.get(th.li - 1, nb);
         add_link<0, -1>(cur, nb, p0, f);
@@ -485,14 +528,26 @@ __device__ __forceinline__ void plane_step(LDS &L, const StepArgs &a, const Tile
         L.get(th.li + COLS, nb);
         add_link<1, +1>(cur, nb, p0, f);
     }
-    if (z > 0 || zper)
+    // the z ghost cells are built where they are used: filling window registers with them
+    // inside the plane loop costs the whole loop registers
+    if (z > 0 || zper) {
         add_link<2, -1>(cur, prv, p0, f);
-    if (z + 1 < g.nz || zper)
+    } else if (zres) {
+        Cell<S, FID, MSD, EXT> gz;
+        ghost_cell(gz, a.ghost, 4);
+        add_link<2, -1>(cur, gz, p0, f);
+    }
+    if (z + 1 < g.nz || zper) {
         add_link<2, +1>(cur, nxt, p0, f);
+    } else if (zres) {
+        Cell<S, FID, MSD, EXT> gz;
+        ghost_cell(gz, a.ghost, 5);
+        add_link<2, +1>(cur, gz, p0, f);
+    }
     const int64_t pz = plane * z;
     const S theta = FID ? ld(TH + pz, own.bs) : S(0);
     const int r = MAXR == 1 ? 0 : ld(a.region + pz, own.b1);
-    finish_site<S, FID, MSD, MAXR>(cur, f, theta, r, dst, pz, own, acc);
+    finish_site<S, FID, MSD, EXT, MAXR>(cur, f, theta, r, dst, pz, own, acc);
 }
 
 #ifndef LPC_MIN_WAVES
@@ -507,14 +562,16 @@ __device__ __forceinline__ void plane_step(LDS &L, const StepArgs &a, const Tile
 // The halo sites (a row below and above the tile, a column left and right of it; wrapped
 // on periodic axes, absent across closed faces) are spread over threads, one site each,
 // and fetched one plane ahead. Plane offsets are workgroup-uniform; each thread keeps only
-// the 32-bit byte offsets of its column.
-template <typename S, bool FID, bool MSD, int MAXR, int TX>
+// the 32-bit byte offsets of its column. Beyond a reservoir face in x or y the halo slot
+// holds the face's ghost cell, set once and never reloaded; in z the ghost cell is built
+// at the first or last plane where its link is added.
+template <typename S, bool FID, bool MSD, bool EXT, int MAXR, int TX>
 __device__ __forceinline__ void sweep_tile(const StepArgs &a, const SweepPlan &p, int64_t blk)
 {
     constexpr int TY = kThreads / TX, COLS = TX + 2, NL = COLS * (TY + 2);
     static_assert(TX * TY >= 2 * TX + 2 * TY, "one halo site per thread");
-    using C = Cell<S, FID, MSD>;
-    __shared__ TileLds<S, FID, MSD, NL> L0, L1;
+    using C = Cell<S, FID, MSD, EXT>;
+    __shared__ TileLds<S, FID, MSD, EXT, NL> L0, L1;
     __shared__ double red[(kThreads / kWave) * (3 * MAXR + 6)];
     const Geometry &g = a.g;
     int bx, by, bz;
@@ -525,22 +582,24 @@ __device__ __forceinline__ void sweep_tile(const StepArgs &a, const SweepPlan &p
     const int x = x0 + tx, y = y0 + ty;
     const int cols = min(TX, g.nx - x0), rows = min(TY, g.ny - y0);
     const bool xper = g.bc[0] == 0, yper = g.bc[1] == 0, zper = g.bc[2] == 0;
+    const bool xres = EXT && g.bc[0] == kBcReservoir, yres = EXT && g.bc[1] == kBcReservoir;
     TileThread th;
     th.act = tx < cols && ty < rows;
-    th.has_xm = x > 0 || xper;
-    th.has_xp = x + 1 < g.nx || xper;
-    th.has_ym = y > 0 || yper;
-    th.has_yp = y + 1 < g.ny || yper;
+    th.has_xm = x > 0 || xper || xres;
+    th.has_xp = x + 1 < g.nx || xper || xres;
+    th.has_ym = y > 0 || yper || yres;
+    th.has_yp = y + 1 < g.ny || yper || yres;
     const uint32_t col = th.act ? static_cast<uint32_t>(x + g.nx * y) : 0u;
     th.own = {col * 8u, col * static_cast<uint32_t>(sizeof(S)), col};
     th.li = (ty + 1) * COLS + tx + 1;
     th.hslot = -1;
     {
-        int hx = -1, hy = -1;
+        int hx = -1, hy = -1, face = -1;
         if (t < TX) {                                   // row below the tile
             if (t < cols) {
                 hx = x0 + t;
                 hy = y0 > 0 ? y0 - 1 : (yper ? g.ny - 1 : -1);
+                face = hy < 0 && yres ? 2 : -1;
                 th.hslot = t + 1;
             }
         } else if (t < 2 * TX) {                        // row above the tile
@@ -548,6 +607,7 @@ __device__ __forceinline__ void sweep_tile(const StepArgs &a, const SweepPlan &p
             if (u < cols) {
                 hx = x0 + u;
                 hy = y0 + rows < g.ny ? y0 + rows : (yper ? (y0 + rows) % g.ny : -1);
+                face = hy < 0 && yres ? 3 : -1;
                 th.hslot = (rows + 1) * COLS + u + 1;
             }
         } else if (t < 2 * TX + TY) {                   // column left of the tile
@@ -555,6 +615,7 @@ __device__ __forceinline__ void sweep_tile(const StepArgs &a, const SweepPlan &p
             if (v < rows) {
                 hy = y0 + v;
                 hx = x0 > 0 ? x0 - 1 : (xper ? g.nx - 1 : -1);
+                face = hx < 0 && xres ? 0 : -1;
                 th.hslot = (v + 1) * COLS;
             }
         } else if (t < 2 * TX + 2 * TY) {               // column right of the tile
@@ -562,15 +623,19 @@ __device__ __forceinline__ void sweep_tile(const StepArgs &a, const SweepPlan &p
             if (v < rows) {
                 hy = y0 + v;
                 hx = x0 + cols < g.nx ? x0 + cols : (xper ? (x0 + cols) % g.nx : -1);
+                face = hx < 0 && xres ? 1 : -1;
                 th.hslot = (v + 1) * COLS + cols + 1;
             }
         }
-        if (hx < 0 || hy < 0)
+        if ((hx < 0 || hy < 0) && face < 0)
             th.hslot = -1;
-        const uint32_t hcol = th.hslot >= 0 ? static_cast<uint32_t>(hx + g.nx * hy) : 0u;
+        th.hghost = th.hslot >= 0 ? face : -1;
+        const uint32_t hcol = th.hslot >= 0 && face < 0 ? static_cast<uint32_t>(hx + g.nx * hy)
+                                                        : 0u;
         th.halo = {hcol * 8u, hcol * static_cast<uint32_t>(sizeof(S)), hcol};
     }
     const S *F = static_cast<const S *>(a.F);
+    const S *MU = static_cast<const S *>(a.mu);
     const S *TH = static_cast<const S *>(a.theta);
     const View<S> src = typed<S>(a.src);
     const View<S> dst = typed<S>(a.dst);
@@ -580,29 +645,37 @@ __device__ __forceinline__ void sweep_tile(const StepArgs &a, const SweepPlan &p
     RecAcc<MAXR> acc;
     acc.zero();
     if (th.act) {
-        load_cell(w1, src, F, plane * z0, th.own);
+        load_cell(w1, src, F, MU, plane * z0, th.own);
         const int zm = z0 > 0 ? z0 - 1 : (zper ? g.nz - 1 : -1);
         const int zp = z0 + 1 < g.nz ? z0 + 1 : (zper ? (z0 + 1) % g.nz : -1);
         if (zm >= 0)
-            load_cell(w0, src, F, plane * zm, th.own);
+            load_cell(w0, src, F, MU, plane * zm, th.own);
         if (zp >= 0)
-            load_cell(w2, src, F, plane * zp, th.own);
+            load_cell(w2, src, F, MU, plane * zp, th.own);
     }
-    if (th.hslot >= 0)
-        load_cell(halo, src, F, plane * z0, th.halo);
+    if (th.hslot >= 0) {
+        if (EXT && th.hghost >= 0)
+            ghost_cell(halo, a.ghost, th.hghost);
+        else
+            load_cell(halo, src, F, MU, plane * z0, th.halo);
+    }
     // roles (prv, cur, nxt, in-flight) rotate through w0..w3 with period 4; LDS buffers
     // alternate with period 2
     for (int z = z0; z < z1; z += 4) {
-        plane_step<S, FID, MSD, MAXR, TX>(L0, a, th, src, dst, F, TH, plane, z, z1, w0, w1, w2, w3, halo, acc);
+        plane_step<S, FID, MSD, EXT, MAXR, TX>(L0, a, th, src, dst, F, MU, TH, plane, z, z1, w0,
+                                                    w1, w2, w3, halo, acc);
         if (z + 1 >= z1)
             break;
-        plane_step<S, FID, MSD, MAXR, TX>(L1, a, th, src, dst, F, TH, plane, z + 1, z1, w1, w2, w3, w0, halo, acc);
+        plane_step<S, FID, MSD, EXT, MAXR, TX>(L1, a, th, src, dst, F, MU, TH, plane, z + 1, z1, w1,
+                                                    w2, w3, w0, halo, acc);
         if (z + 2 >= z1)
             break;
-        plane_step<S, FID, MSD, MAXR, TX>(L0, a, th, src, dst, F, TH, plane, z + 2, z1, w2, w3, w0, w1, halo, acc);
+        plane_step<S, FID, MSD, EXT, MAXR, TX>(L0, a, th, src, dst, F, MU, TH, plane, z + 2, z1, w2,
+                                                    w3, w0, w1, halo, acc);
         if (z + 3 >= z1)
             break;
-        plane_step<S, FID, MSD, MAXR, TX>(L1, a, th, src, dst, F, TH, plane, z + 3, z1, w3, w0, w1, w2, halo, acc);
+        plane_step<S, FID, MSD, EXT, MAXR, TX>(L1, a, th, src, dst, F, MU, TH, plane, z + 3, z1, w3,
+                                                    w0, w1, w2, halo, acc);
     }
     __syncthreads();
     block_reduce<MAXR, kThreads / kWave>(acc, a.R, a.K, a.partials, p.nblocks, blk, red);
@@ -612,7 +685,7 @@ __device__ __forceinline__ void sweep_tile(const StepArgs &a, const SweepPlan &p
 // tile w - prefix[l] of item l, prefix[l] <= w < prefix[l + 1]. The items hold the views
 // of the step with parity 0; parity 1 swaps source and destination. Each lattice keeps its
 // own plan, so a lattice gives the same bits alone (a list of one) and in any batch.
-template <typename S, bool FID, bool MSD, int MAXR, int TX>
+template <typename S, bool FID, bool MSD, bool EXT, int MAXR, int TX>
 __global__ __launch_bounds__(kThreads, LPC_MIN_WAVES) void k_sweep_tile(
     const SweepItem *__restrict__ items, const int64_t *__restrict__ prefix, int32_t n_items,
     int64_t total, int64_t padded, int32_t parity, int64_t slot)
@@ -636,7 +709,7 @@ __global__ __launch_bounds__(kThreads, LPC_MIN_WAVES) void k_sweep_tile(
         a.dst = t;
     }
     a.partials += slot * a.K * p.nblocks;
-    sweep_tile<S, FID, MSD, MAXR, TX>(a, p, w - prefix[lo]);
+    sweep_tile<S, FID, MSD, EXT, MAXR, TX>(a, p, w - prefix[lo]);
 }
 
 template <typename S, bool FID, bool MSD, int MAXR>
@@ -740,11 +813,13 @@ __global__ void k_store_field(const double *src, S *dst, int64_t n, double scale
 }
 
 template <typename S>
-__global__ void k_init_state(View<S> st, bool fid, bool msd, const double *rho_src, int64_t n)
+__global__ void k_init_state(View<S> st, bool fid, bool msd, const double *rho_src, const S *F,
+                             int64_t n)
 {
     for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const double r = rho_src ? rho_src[i] : 1.0;
+        const bool open = static_cast<double>(F[i]) < kBlockedTest;   // not solid matrix
+        const double r = open ? (rho_src ? rho_src[i] : 1.0) : 0.0;
         st.rho[i] = r;
         if (fid) {
             st.re[i] = static_cast<S>(r);
@@ -757,6 +832,14 @@ __global__ void k_init_state(View<S> st, bool fid, bool msd, const double *rho_s
             }
         }
     }
+}
+
+template <typename S>
+__global__ void k_fill(S *dst, int64_t n, S value)
+{
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        dst[i] = value;
 }
 
 constexpr int kWeightBlocks = 1024;
@@ -817,7 +900,7 @@ int grid_for(int64_t n, int threads)
 // ---------------------------------------------------------------------------- dispatch
 
 struct RecordLauncher {
-    template <typename S, bool FID, bool MSD, int MAXR>
+    template <typename S, bool FID, bool MSD, bool, int MAXR>
     static hipError_t go(const SweepPlan &p, const StepArgs &a, hipStream_t s)
     {
         const int64_t padded = (p.nblocks + 7) / 8 * 8;
@@ -828,47 +911,55 @@ struct RecordLauncher {
 };
 
 struct ListLauncher {
-    template <typename S, bool FID, bool MSD, int MAXR>
+    template <typename S, bool FID, bool MSD, bool EXT, int MAXR>
     static hipError_t go(const SweepPlan &, const StepArgs &, hipStream_t s, const StepList *L)
     {
         const int64_t padded = (L->total + 7) / 8 * 8;
         const dim3 grid(static_cast<unsigned>(padded)), block(kThreads);
         if (L->tile_x == 64)
-            hipLaunchKernelGGL((k_sweep_tile<S, FID, MSD, MAXR, 64>), grid, block, 0, s, L->items,
+            hipLaunchKernelGGL((k_sweep_tile<S, FID, MSD, EXT, MAXR, 64>), grid, block, 0, s, L->items,
                                L->prefix, L->n_items, L->total, padded, L->parity, L->slot);
         else if (L->tile_x == 32)
-            hipLaunchKernelGGL((k_sweep_tile<S, FID, MSD, MAXR, 32>), grid, block, 0, s, L->items,
+            hipLaunchKernelGGL((k_sweep_tile<S, FID, MSD, EXT, MAXR, 32>), grid, block, 0, s, L->items,
                                L->prefix, L->n_items, L->total, padded, L->parity, L->slot);
         else
-            hipLaunchKernelGGL((k_sweep_tile<S, FID, MSD, MAXR, 16>), grid, block, 0, s, L->items,
+            hipLaunchKernelGGL((k_sweep_tile<S, FID, MSD, EXT, MAXR, 16>), grid, block, 0, s, L->items,
                                L->prefix, L->n_items, L->total, padded, L->parity, L->slot);
         return hipGetLastError();
     }
 };
 
-template <typename L, typename S, bool FID, bool MSD, typename... X>
+template <typename L, typename S, bool FID, bool MSD, bool EXT, typename... X>
 hipError_t by_regions(const SweepPlan &p, const StepArgs &a, hipStream_t s, X... x)
 {
     if (a.R == 1)
-        return L::template go<S, FID, MSD, 1>(p, a, s, x...);
+        return L::template go<S, FID, MSD, EXT, 1>(p, a, s, x...);
     if (a.R == 2)
-        return L::template go<S, FID, MSD, 2>(p, a, s, x...);
+        return L::template go<S, FID, MSD, EXT, 2>(p, a, s, x...);
     if (a.R <= 4)
-        return L::template go<S, FID, MSD, 4>(p, a, s, x...);
-    return L::template go<S, FID, MSD, 8>(p, a, s, x...);
+        return L::template go<S, FID, MSD, EXT, 4>(p, a, s, x...);
+    return L::template go<S, FID, MSD, EXT, 8>(p, a, s, x...);
+}
+
+template <typename L, typename S, bool EXT, typename... X>
+hipError_t by_fields(const SweepPlan &p, const StepArgs &a, hipStream_t s, X... x)
+{
+    const bool fid = a.track & 1u, msd = a.track & 2u;
+    if (fid && msd)
+        return by_regions<L, S, true, true, EXT>(p, a, s, x...);
+    if (fid)
+        return by_regions<L, S, true, false, EXT>(p, a, s, x...);
+    if (msd)
+        return by_regions<L, S, false, true, EXT>(p, a, s, x...);
+    return by_regions<L, S, false, false, EXT>(p, a, s, x...);
 }
 
 template <typename L, typename S, typename... X>
 hipError_t by_track(const SweepPlan &p, const StepArgs &a, hipStream_t s, X... x)
 {
-    const bool fid = a.track & 1u, msd = a.track & 2u;
-    if (fid && msd)
-        return by_regions<L, S, true, true>(p, a, s, x...);
-    if (fid)
-        return by_regions<L, S, true, false>(p, a, s, x...);
-    if (msd)
-        return by_regions<L, S, false, true>(p, a, s, x...);
-    return by_regions<L, S, false, false>(p, a, s, x...);
+    if (a.track & kVariantExtended)
+        return by_fields<L, S, true>(p, a, s, x...);
+    return by_fields<L, S, false>(p, a, s, x...);
 }
 
 template <typename L, typename... X>
@@ -960,12 +1051,12 @@ SweepPlan with_z_chunk(SweepPlan p, const Geometry &g, int32_t zc)
 }
 
 struct OccupancyQuery {
-    template <typename S, bool FID, bool MSD, int MAXR>
+    template <typename S, bool FID, bool MSD, bool EXT, int MAXR>
     static hipError_t go(const SweepPlan &, const StepArgs &, hipStream_t, int *out)
     {
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            out, reinterpret_cast<const void *>(&k_sweep_tile<S, FID, MSD, MAXR, 64>), kThreads,
-            0);
+            out, reinterpret_cast<const void *>(&k_sweep_tile<S, FID, MSD, EXT, MAXR, 64>),
+            kThreads, 0);
     }
 };
 
@@ -1033,16 +1124,29 @@ hipError_t launch_store_field(int32_t precision, const double *src, void *dst, i
 }
 
 hipError_t launch_init_state(int32_t precision, uint32_t track, const StateView &st,
-                             const double *rho_src, int64_t n, hipStream_t s)
+                             const double *rho_src, const void *F, int64_t n, hipStream_t s)
 {
     const int g = grid_for(n, 256);
     const bool fid = track & 1u, msd = track & 2u;
     if (precision == 0)
         hipLaunchKernelGGL(k_init_state<double>, dim3(g), dim3(256), 0, s, typed<double>(st), fid,
-                           msd, rho_src, n);
+                           msd, rho_src, static_cast<const double *>(F), n);
     else
         hipLaunchKernelGGL(k_init_state<float>, dim3(g), dim3(256), 0, s, typed<float>(st), fid,
-                           msd, rho_src, n);
+                           msd, rho_src, static_cast<const float *>(F), n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_field(int32_t precision, void *dst, int64_t n, double value,
+                             hipStream_t s)
+{
+    const int g = grid_for(n, 256);
+    if (precision == 0)
+        hipLaunchKernelGGL(k_fill<double>, dim3(g), dim3(256), 0, s, static_cast<double *>(dst), n,
+                           value);
+    else
+        hipLaunchKernelGGL(k_fill<float>, dim3(g), dim3(256), 0, s, static_cast<float *>(dst), n,
+                           static_cast<float>(value));
     return hipGetLastError();
 }
 

@@ -13,7 +13,7 @@ import torch
 from . import _native as N
 from ._native import LpcError  # noqa: F401  (re-exported)
 
-BC = {"periodic": N.BC_PERIODIC, "closed": N.BC_CLOSED}
+BC = {"periodic": N.BC_PERIODIC, "closed": N.BC_CLOSED, "reservoir": N.BC_RESERVOIR}
 PRECISION = {"fp64": N.PREC_FP64, "mixed": N.PREC_MIXED}
 INIT = {"uniform": N.INIT_UNIFORM, "boltzmann": N.INIT_BOLTZMANN, "user": N.INIT_USER}
 
@@ -22,9 +22,19 @@ def _ptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
+def p_hop_from_residence_time(tau_s: float, dt_s: float) -> float:
+    """Attempt probability per neighbour for a mean residence time tau on a free site:
+    a particle leaves with probability 6 p_hop per step, so tau = dt / (6 p_hop) (the
+    residence times of section 4, 1 ms and 0.2 ms at dt = 5 us, give p_hop = 1/1200 and
+    1/240)."""
+    if tau_s < dt_s:
+        raise ValueError("the residence time must be at least one time step")
+    return dt_s / (6.0 * tau_s)
+
+
 def make_config(shape_xyz, bc=("periodic",) * 3, precision="fp64", track=("fid", "msd"),
                 n_regions=1, p_hop=1.0 / 7.0, dt_s=5e-6, larmor_hz=400e6, spacing_m=0.5e-9,
-                max_records=1, conservation_tol=1e-12) -> N.Config:
+                max_records=1, conservation_tol=1e-12, mobility=False) -> N.Config:
     cfg = N.Config()
     for a in range(3):
         cfg.n[a] = int(shape_xyz[a])
@@ -36,7 +46,7 @@ def make_config(shape_xyz, bc=("periodic",) * 3, precision="fp64", track=("fid",
         t |= {"fid": N.TRACK_FID, "msd": N.TRACK_MSD}[name]
     cfg.track = t
     cfg.n_regions = int(n_regions)
-    cfg.reserved = 0
+    cfg.options = N.OPT_MOBILITY if mobility else 0
     cfg.p_hop = float(p_hop)
     cfg.dt_s = float(dt_s)
     cfg.larmor_hz = float(larmor_hz)
@@ -60,9 +70,10 @@ class Lattice:
 
     def __init__(self, shape_xyz, bc=("periodic",) * 3, precision="fp64", track=("fid", "msd"),
                  n_regions=1, p_hop=1.0 / 7.0, dt_s=5e-6, larmor_hz=400e6, spacing_m=0.5e-9,
-                 max_records=1, conservation_tol=1e-12, device=None, stream=None):
+                 max_records=1, conservation_tol=1e-12, device=None, stream=None,
+                 mobility=False):
         self.cfg = make_config(shape_xyz, bc, precision, track, n_regions, p_hop, dt_s,
-                               larmor_hz, spacing_m, max_records, conservation_tol)
+                               larmor_hz, spacing_m, max_records, conservation_tol, mobility)
         self.shape_xyz = tuple(int(v) for v in shape_xyz)
         self.n_sites = int(np.prod(self.shape_xyz))
         self.n_regions = int(n_regions)
@@ -129,8 +140,22 @@ class Lattice:
         return a
 
     def set_free_energy(self, F_kT):
+        """Free energies in kT; +inf marks inaccessible sites (solid matrix)."""
         a = self._sites(F_kT, np.float64)
         N.call("lpc_set_free_energy", self.handle, _ptr(a), a.size)
+
+    def set_mobility(self, mu):
+        """Per-site mobility in [0, 1]; the link i-j is scaled by min(mu_i, mu_j). Needs
+        mobility=True at construction."""
+        a = self._sites(mu, np.float64)
+        N.call("lpc_set_mobility", self.handle, _ptr(a), a.size)
+
+    def set_reservoir(self, axis, side, F_kT=0.0, rho=0.0, m=0.0):
+        """Ghost site beyond face `side` (0 low, 1 high) of a reservoir axis: free energy,
+        population and complex magnetisation."""
+        m = complex(m)
+        N.call("lpc_set_reservoir", self.handle, int(axis), int(side), float(F_kT), float(rho),
+               m.real, m.imag)
 
     def set_shift(self, delta_ppm):
         a = self._sites(delta_ppm, np.float64)

@@ -3,6 +3,7 @@ include/lpc.h declares, and validates configurations before touching the device.
 import ctypes
 import os
 
+import numpy as np
 import pytest
 
 from paper_2603_22553_amd import _native as N
@@ -76,7 +77,7 @@ def test_footprint_byte_model(lib):
 
 @pytest.mark.parametrize("field,value", [
     ("p_hop", 0.2), ("p_hop", -0.01), ("n_regions", 0), ("n_regions", 9), ("max_records", 0),
-    ("precision", 5), ("track", 8), ("dt_s", 0.0), ("reserved", 1), ("conservation_tol", -1.0),
+    ("precision", 5), ("track", 8), ("dt_s", 0.0), ("options", 2), ("conservation_tol", -1.0),
 ])
 def test_config_rejected(lib, field, value):
     st, _ = _footprint(_cfg(8, **{field: value}))
@@ -87,8 +88,17 @@ def test_config_rejected(lib, field, value):
 def test_bad_shape_rejected(lib):
     st, _ = _footprint(_cfg(8, n=(0, 4, 4)))
     assert st == N.LPC_ERR_ARG
-    st, _ = _footprint(_cfg(8, bc=(0, 2, 0)))
+    st, _ = _footprint(_cfg(8, bc=(0, 3, 0)))
     assert st == N.LPC_ERR_ARG
+    st, _ = _footprint(_cfg(8, bc=(0, N.BC_RESERVOIR, 0)))     # reservoir axes are valid
+    assert st == N.LPC_OK
+
+
+def test_mobility_field_in_footprint(lib):
+    """LPC_OPT_MOBILITY adds one storage-type value per site to the arena."""
+    _, plain = _footprint(_cfg(32))
+    _, mob = _footprint(_cfg(32, options=N.OPT_MOBILITY))
+    assert mob - plain >= 32 ** 3 * 8
 
 
 def test_null_arguments(lib):
@@ -100,3 +110,18 @@ def test_null_arguments(lib):
 def test_max_p_hop_accepted(lib):
     st, _ = _footprint(_cfg(4, p_hop=1.0 / 6.0))
     assert st == N.LPC_OK
+
+
+def test_p_hop_from_residence_time():
+    """A free site is left with probability 6 p_hop per step, so its mean residence time
+    is dt / (6 p_hop): the 1 ms and 0.2 ms of the paper's runs at dt = 5 us."""
+    from paper_2603_22553_amd.lattice import p_hop_from_residence_time
+    assert p_hop_from_residence_time(1e-3, 5e-6) == pytest.approx(1.0 / 1200.0, rel=1e-15)
+    assert p_hop_from_residence_time(0.2e-3, 5e-6) == pytest.approx(1.0 / 240.0, rel=1e-15)
+    # geometric stay: mean number of steps before leaving = 1 / (6 p_hop)
+    p = p_hop_from_residence_time(7e-5, 5e-6)
+    k = np.arange(1, 20000)
+    mean_steps = np.sum(k * (1 - 6 * p) ** (k - 1) * 6 * p)
+    assert mean_steps * 5e-6 == pytest.approx(7e-5, rel=1e-9)
+    with pytest.raises(ValueError):
+        p_hop_from_residence_time(1e-6, 5e-6)
