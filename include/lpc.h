@@ -116,8 +116,8 @@ lpc_status lpc_destroy(lpc_lattice *lat);
 
 /* Site free energies in kT (Eq. (1)); n must be nx*ny*nz. F = +INFINITY marks an
  * inaccessible site (solid matrix, section 2.1 and Fig. 1): it holds nothing and every
- * move towards it is rejected. NaN or -Inf -> LPC_ERR_NONFINITE; a finite |F| above 1e30
- * -> LPC_ERR_ARG. */
+ * move towards it is rejected. NaN or -Inf -> LPC_ERR_NONFINITE; a finite |F| above 1e30,
+ * or accessible free energies spanning more than 1400 kT -> LPC_ERR_ARG. */
 lpc_status lpc_set_free_energy(lpc_lattice *lat, const double *F_kT, int64_t n);
 /* Per-site mobility mu in [0, 1] (n values; needs LPC_OPT_MOBILITY, else LPC_ERR_STATE;
  * out of range -> LPC_ERR_ARG, NaN -> LPC_ERR_NONFINITE). Starts at 1 everywhere. */

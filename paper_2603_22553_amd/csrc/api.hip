@@ -49,6 +49,7 @@ constexpr int64_t kChunkMax = 256;                    // steps finalised togethe
 constexpr int kScalars = 64;
 constexpr int kGhostValues = 24;   // 6 faces x (F, rho, Re m, Im m)
 constexpr double kMaxFreeEnergy = 1e30;
+constexpr double kMaxFreeEnergySpan = 1400.0;
 constexpr int kArgmaxParts = 256;
 
 // Smallest power of two >= 8 * samples: the default zero-filled FFT length.
@@ -218,6 +219,7 @@ struct lpc_lattice {
     bool initialized = false;
     int64_t steps_done = 0;
     double Fmin = 0.0;
+    double Fmid = 0.0;                        // centre of the accessible free energies
     int64_t n_open = 0;                       // accessible sites (F < +inf)
     double ghost[kGhostValues] = {};          // host copy of the reservoir ghost table
     int occupancy = 1, cus = 1;      // resident sweep workgroups per CU, compute units
@@ -262,6 +264,7 @@ struct lpc_lattice {
         a.R = cfg.n_regions;
         a.K = L.K;
         a.p0 = cfg.p_hop;
+        a.fc = Fmid;
         a.F = at(L.off_F);
         a.theta = at(L.off_theta);
         a.region = at<uint8_t>(L.off_region);
@@ -282,6 +285,21 @@ lpc_status use_device(const lpc_lattice *lat)
     LPC_HIP(hipGetDevice(&d));
     if (d != lat->device)
         LPC_HIP(hipSetDevice(lat->device));
+    return LPC_OK;
+}
+
+// Uploads the one-entry work list of lpc_run (plan and step arguments) after anything it
+// holds has changed. The lattice's stream must be idle.
+lpc_status upload_solo(lpc_lattice *lat)
+{
+    SoloTables tables{};
+    tables.item = lat->sweep_item(0);
+    tables.prefix[0] = 0;
+    tables.prefix[1] = lat->L.plan.nblocks;
+    tables.fin = lat->finalize_item(0);
+    tables.kprefix[0] = 0;
+    tables.kprefix[1] = lat->L.K;
+    LPC_HIP(hipMemcpy(lat->solo(), &tables, sizeof tables, hipMemcpyHostToDevice));
     return LPC_OK;
 }
 
@@ -519,7 +537,7 @@ lpc_status lpc_set_free_energy(lpc_lattice *lat, const double *F_kT, int64_t n)
     const double blocked =
         lat->cfg.precision == LPC_PREC_FP64 ? lpc::kBlockedF64 : lpc::kBlockedF32;
     std::vector<double> host;
-    double fmin = INFINITY;
+    double fmin = INFINITY, fmax = -INFINITY;
     int64_t open = 0;
     for (int64_t i = 0; i < n; ++i) {
         const double f = F_kT[i];
@@ -535,15 +553,23 @@ lpc_status lpc_set_free_energy(lpc_lattice *lat, const double *F_kT, int64_t n)
             return fail(LPC_ERR_ARG, "|F[%lld]| = %g exceeds %g kT", (long long)i, std::fabs(f),
                         kMaxFreeEnergy);
         fmin = f < fmin ? f : fmin;
+        fmax = f > fmax ? f : fmax;
         ++open;
     }
+    // the FP64 sweep works with e^{+-(F - centre)}, which must stay finite
+    if (open > 0 && fmax - fmin > kMaxFreeEnergySpan)
+        return fail(LPC_ERR_ARG, "accessible free energies span %g kT, more than %g", fmax - fmin,
+                    kMaxFreeEnergySpan);
     if (lpc_status s = use_device(lat))
         return s;
     if (lpc_status s = upload_field(lat, host.empty() ? F_kT : host.data(),
                                     lat->at(lat->L.off_F), 1.0))
         return s;
     lat->Fmin = open > 0 ? fmin : 0.0;
+    lat->Fmid = open > 0 ? 0.5 * (fmin + fmax) : 0.0;
     lat->n_open = open;
+    if (lpc_status s = upload_solo(lat))
+        return s;
     return ok();
 }
 
@@ -1514,15 +1540,9 @@ lpc_status lpc_set_plan(lpc_lattice *lat, int32_t tile_x, int32_t zc)
     Layout L = lat->L;
     L.plan = p;
     set_chunk(L);
-    SoloTables tables{};
     lat->L = L;
-    tables.item = lat->sweep_item(0);
-    tables.prefix[0] = 0;
-    tables.prefix[1] = p.nblocks;
-    tables.fin = lat->finalize_item(0);
-    tables.kprefix[0] = 0;
-    tables.kprefix[1] = L.K;
-    LPC_HIP(hipMemcpy(lat->solo(), &tables, sizeof tables, hipMemcpyHostToDevice));
+    if (lpc_status s = upload_solo(lat))
+        return s;
     return ok();
 }
 

@@ -53,6 +53,7 @@ struct StepArgs {
     int32_t R;           // regions
     int32_t K;           // record width
     double p0;
+    double fc;             // centre of the accessible free energies (FP64 cell weights)
     const void *F;
     const void *theta;
     const uint8_t *region;

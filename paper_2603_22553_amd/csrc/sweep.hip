@@ -5,9 +5,14 @@
 // displacement moments M1, M2, plus the per-step sums over sites of Eqs. (11)-(12).
 //
 // Per site i the step gathers from the six neighbours j with the hop probabilities of
-// Eq. (1) (one exponential per link gives both directions: p(i->j) = p0 e^{-|dF|} if
-// F_j > F_i else p0, and p(j->i) the other way round) and keeps the staying fraction
-// stay(i) = 1 - P_out(i), P_out(i) = sum_j p(i->j):
+// Eq. (1), p(i->j) = p0 min(1, e^{F_i - F_j}), and keeps the staying fraction
+// stay(i) = 1 - P_out(i), P_out(i) = sum_j p(i->j). The float path takes one exponential
+// per link for both directions (p0 e^{-|dF|} one way, p0 the other). The FP64 path turns
+// each cell's free energy into the two factors E = e^{F - c} and G = e^{c - F} once, at the
+// cell's first use (c centres the accessible range), and a link's acceptances are the
+// products E_i G_j and E_j G_i clipped at 1: two exponentials per loaded cell instead of
+// one per link end. The two ends of a link form the same products, so they see the same
+// probabilities bit for bit.
 //     x'_i = stay(i) x_i + sum_j p(j->i) x_j'        (x_j' with the hop's displacement)
 // Totals are only preserved step after step if stay(i) + P_out(i) is exactly one, so the
 // rounding of P_out must not repeat the same bias every step:
@@ -27,8 +32,8 @@
 // ghost cell of fixed values (F, rho, m, zero moments, mobility 1); lattices that use
 // neither run the plain variant, which carries none of their registers.
 // Magnetisation rotates after the gather by the destination's phase (Eq. (13)), applied
-// as m + m (cos t - 1) + i m sin t with cos t - 1 = -2 sin^2(t/2), which keeps |m| from
-// drifting when t is stored in float.
+// as m + m (cos t - 1) + i m sin t with cos t - 1 evaluated without cancellation, which
+// keeps |m| from drifting when t is stored in float.
 //
 // Per-step sums are deterministic: each workgroup reduces its sites with wave-level
 // butterflies and a fixed-order pass over its waves into one partial per record entry,
@@ -192,11 +197,35 @@ __device__ inline int64_t logical_block(int64_t b, int64_t padded)
 template <typename S, bool FID, bool MSD, bool EXT>
 struct Cell {
     double rho;
-    S F;
+    S F;      // FP64 path: free energy when loaded, then E = e^{F - c} once weighed
+    S G;      // FP64 path: G = e^{c - F} once weighed
     S re, im;
     S m1[3], m2[3];
     S mu;
 };
+
+// Whether the storage type's path works with per-cell Boltzmann factors (FP64) or with one
+// exponential per link (float).
+template <typename S>
+struct PerCellWeights {
+    static constexpr bool on = false;
+};
+template <>
+struct PerCellWeights<double> {
+    static constexpr bool on = true;
+};
+
+// FP64 path: replaces the loaded free energy by E = e^{F - c} and adds G = 1/E = e^{c - F}.
+// An inaccessible site (sentinel F) gets E = inf, G = 0, hence zero acceptance towards it.
+template <typename S, bool FID, bool MSD, bool EXT>
+__device__ inline void weigh(Cell<S, FID, MSD, EXT> &c, double fc)
+{
+    if (PerCellWeights<S>::on) {
+        const double e = exp(static_cast<double>(c.F) - fc);
+        c.F = static_cast<S>(e);
+        c.G = static_cast<S>(1.0 / e);
+    }
+}
 
 // Byte offsets of one column (or halo column) in the 8-byte, S-sized and 1-byte arrays.
 struct Off {
@@ -226,12 +255,14 @@ __device__ inline void load_cell(Cell<S, FID, MSD, EXT> &c, const View<S> &v, co
 }
 
 // The fixed ghost site beyond reservoir face `face` (2 * axis + side): free energy,
-// population and magnetisation from the table, zero moments, mobility 1.
+// population and magnetisation from the table, zero moments, mobility 1; weighed.
 template <typename S, bool FID, bool MSD, bool EXT>
-__device__ inline void ghost_cell(Cell<S, FID, MSD, EXT> &c, const double *ghost, int face)
+__device__ inline void ghost_cell(Cell<S, FID, MSD, EXT> &c, const double *ghost, int face,
+                                  double fc)
 {
     const double *v = ghost + 4 * face;
     c.F = static_cast<S>(v[0]);
+    weigh(c, fc);
     c.rho = v[1];
     if (FID) {
         c.re = static_cast<S>(v[2]);
@@ -258,21 +289,27 @@ __device__ inline float fast_exp(float v)
 {
     return __expf(v);
 }
-__device__ inline double fast_exp(double v)
-{
-    return exp(v);
-}
 
-// Hop probabilities of one link in the arithmetic type, Eq. (1): p_out = p(i->j),
-// p_in = p(j->i). The same (|dF|, direction) gives bit-identical values at both ends.
-template <typename S>
-__device__ inline void link_pair(S Fi, S Fj, S p0, S &p_out, S &p_in)
+// Hop probabilities of one link in float, Eq. (1): p_out = p(i->j), p_in = p(j->i). The
+// same (|dF|, direction) gives bit-identical values at both ends.
+__device__ inline void link_pair(float Fi, float Fj, float p0, float &p_out, float &p_in)
 {
-    const S dF = Fj - Fi;
-    const S pe = p0 * fast_exp(-(dF > S(0) ? dF : -dF));
-    const bool up = dF > S(0);
+    const float dF = Fj - Fi;
+    const float pe = p0 * fast_exp(-(dF > 0.0f ? dF : -dF));
+    const bool up = dF > 0.0f;
     p_out = up ? pe : p0;
     p_in = up ? p0 : pe;
+}
+
+// The same from the weighed cells of the FP64 path: the acceptance of i -> j is
+// min(1, e^{F_i - F_j}) = min(1, E_i G_j). The clip is written so that a product that is
+// not a number (only between two inaccessible sites, which hold nothing) gives 1.
+__device__ inline void link_pair_weighed(double Ei, double Gi, double Ej, double Gj, double p0,
+                                         double &p_out, double &p_in)
+{
+    const double ro = Ei * Gj, ri = Ej * Gi;
+    p_out = p0 * (ro < 1.0 ? ro : 1.0);
+    p_in = p0 * (ri < 1.0 ? ri : 1.0);
 }
 
 // Gathers the fields arriving over one link from neighbour `nb`, which lies one hop along
@@ -318,7 +355,7 @@ __device__ inline void add_link(const Cell<double, FID, MSD, EXT> &c,
                                 const Cell<double, FID, MSD, EXT> &nb, double p0, Acc<double> &f)
 {
     double p_out, p_in;
-    link_pair(c.F, nb.F, link_p0(c, nb, p0), p_out, p_in);
+    link_pair_weighed(c.F, c.G, nb.F, nb.G, link_p0(c, nb, p0), p_out, p_in);
     f.rho += exact_flux(p_in, nb.rho, p_out, c.rho);
     f.pout += p_out;
     gather<AX, SGN>(nb, p_in, f);
@@ -355,13 +392,67 @@ __device__ inline double new_rho(double stay, double rho, const Acc<float> &f)
     return fma(stay, rho, f.rho);
 }
 
-__device__ inline void half_angle(double t, double &s, double &c)
+// sin t and cos t - 1 of the per-step phase, without branches (a full-range library sincos
+// next to a short path costs every sweep variant registers). t is reduced to r in
+// [-pi, pi] with 2 pi split into a leading and a trailing part (Cody and Waite), the
+// Maclaurin series of sin and cos - 1 are summed at x = r / 8 (|x| <= pi / 8, where the
+// first omitted terms are below 1e-18 in double and 2e-9 relative in float), and the angle
+// is doubled three times: sin 2x = 2 sin x (1 + (cos x - 1)), cos 2x - 1 =
+// 2 (cos x - 1) (cos x - 1 + 2). Both results stay within 4 ulp, cos t - 1 in relative
+// terms, so small phases lose nothing to cancellation.
+__device__ inline void rotation(double t, double &sn, double &cm1)
 {
-    sincos(0.5 * t, &s, &c);
+    const double k = rint(t * 0.15915494309189535);       // 1 / (2 pi)
+    double r = fma(-k, 6.283185307179586, t);              // 2 pi, leading part
+    r = fma(-k, 2.4492935982947064e-16, r);                // 2 pi, trailing part
+    const double x = 0.125 * r, u = x * x;
+    double a = 1.0 / 6227020800.0;                         // 1/13!
+    a = fma(a, u, -1.0 / 39916800.0);                      // 1/11!
+    a = fma(a, u, 1.0 / 362880.0);                         // 1/9!
+    a = fma(a, u, -1.0 / 5040.0);
+    a = fma(a, u, 1.0 / 120.0);
+    a = fma(a, u, -1.0 / 6.0);
+    double s = fma(x * u, a, x);
+    double b = -1.0 / 87178291200.0;                       // 1/14!
+    b = fma(b, u, 1.0 / 479001600.0);                      // 1/12!
+    b = fma(b, u, -1.0 / 3628800.0);                       // 1/10!
+    b = fma(b, u, 1.0 / 40320.0);
+    b = fma(b, u, -1.0 / 720.0);
+    b = fma(b, u, 1.0 / 24.0);
+    b = fma(b, u, -0.5);
+    double c = u * b;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double s2 = 2.0 * fma(s, c, s);
+        c = 2.0 * c * (c + 2.0);
+        s = s2;
+    }
+    sn = s;
+    cm1 = c;
 }
-__device__ inline void half_angle(float t, float &s, float &c)
+__device__ inline void rotation(float t, float &sn, float &cm1)
 {
-    sincosf(0.5f * t, &s, &c);
+    const float k = rintf(t * 0.15915494f);
+    float r = fmaf(-k, 6.2831855f, t);
+    r = fmaf(-k, -1.7484555e-07f, r);
+    const float x = 0.125f * r, u = x * x;
+    float a = -1.0f / 5040.0f;                             // 1/7!
+    a = fmaf(a, u, 1.0f / 120.0f);
+    a = fmaf(a, u, -1.0f / 6.0f);
+    float s = fmaf(x * u, a, x);
+    float b = 1.0f / 40320.0f;                             // 1/8!
+    b = fmaf(b, u, -1.0f / 720.0f);
+    b = fmaf(b, u, 1.0f / 24.0f);
+    b = fmaf(b, u, -0.5f);
+    float c = u * b;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float s2 = 2.0f * fmaf(s, c, s);
+        c = 2.0f * c * (c + 2.0f);
+        s = s2;
+    }
+    sn = s;
+    cm1 = c;
 }
 
 // New state of a site from its old values and gather sums; stores it and adds its record
@@ -376,9 +467,8 @@ __device__ inline void finish_site(const Cell<S, FID, MSD, EXT> &c, const Acc<S>
     double out_re = 0.0, out_im = 0.0;
     if (FID) {
         const S gre = stay_update(stay, c.re, f.re), gim = stay_update(stay, c.im, f.im);
-        S sh, ch;
-        half_angle(theta, sh, ch);
-        const S sn = S(2) * sh * ch, cm1 = S(-2) * sh * sh;   // sin t, cos t - 1
+        S sn, cm1;                                            // sin t, cos t - 1
+        rotation(theta, sn, cm1);
         const S nre = gre + (gre * cm1 - gim * sn);
         const S nim = gim + (gim * cm1 + gre * sn);
         st(dst.re + pz, o.bs, nre);
@@ -405,6 +495,7 @@ template <typename S, bool FID, bool MSD, bool EXT, int NL>
 struct TileLds {
     double rho[NL];
     S F[NL];
+    S G[PerCellWeights<S>::on ? NL : 1];
     S re[FID ? NL : 1], im[FID ? NL : 1];
     S m1[3][MSD ? NL : 1], m2[3][MSD ? NL : 1];
     S mu[EXT ? NL : 1];
@@ -414,6 +505,8 @@ struct TileLds {
     {
         rho[s] = c.rho;
         F[s] = c.F;
+        if (PerCellWeights<S>::on)
+            G[s] = c.G;
         if (EXT)
             mu[s] = c.mu;
         if (FID) {
@@ -434,6 +527,8 @@ struct TileLds {
     {
         c.rho = rho[s];
         c.F = F[s];
+        if (PerCellWeights<S>::on)
+            c.G = G[s];
         if (EXT)
             c.mu = mu[s];
         if (FID) {
@@ -482,7 +577,7 @@ __device__ __forceinline__ void plane_step(LDS &L, const StepArgs &a, const Tile
                                            const S *MU, const S *TH, int64_t plane, int z,
                                            int z1, const Cell<S, FID, MSD, EXT> &prv,
                                            const Cell<S, FID, MSD, EXT> &cur,
-                                           const Cell<S, FID, MSD, EXT> &nxt,
+                                           Cell<S, FID, MSD, EXT> &nxt,
                                            Cell<S, FID, MSD, EXT> &nx2,
                                            Cell<S, FID, MSD, EXT> &halo, RecAcc<MAXR> &acc)
 {
@@ -491,8 +586,11 @@ __device__ __forceinline__ void plane_step(LDS &L, const StepArgs &a, const Tile
     const bool zper = g.bc[2] == 0, zres = EXT && g.bc[2] == kBcReservoir;
     if (th.act)
         L.put(th.li, cur);
-    if (th.hslot >= 0)
+    if (th.hslot >= 0) {
+        if (!EXT || th.hghost < 0)      // a loaded halo cell; a ghost one is weighed already
+            weigh(halo, a.fc);
         L.put(th.hslot, halo);
+    }
     __syncthreads();
     // The column offsets are re-materialised every plane so that base + offset is not
     // hoisted into per-array 64-bit vector registers: each load then takes the plane's
@@ -510,6 +608,7 @@ __device__ __forceinline__ void plane_step(LDS &L, const StepArgs &a, const Tile
     if (!th.act)
         return;
     const S p0 = static_cast<S>(a.p0);
+    weigh(nxt, a.fc);                   // first use of the plane above (prefetched earlier)
     Acc<S> f{};
     Cell<S, FID, MSD, EXT> nb;
     if (th.has_xm) {
@@ -534,14 +633,14 @@ __device__ __forceinline__ void plane_step(LDS &L, const StepArgs &a, const Tile
         add_link<2, -1>(cur, prv, p0, f);
     } else if (zres) {
         Cell<S, FID, MSD, EXT> gz;
-        ghost_cell(gz, a.ghost, 4);
+        ghost_cell(gz, a.ghost, 4, a.fc);
         add_link<2, -1>(cur, gz, p0, f);
     }
     if (z + 1 < g.nz || zper) {
         add_link<2, +1>(cur, nxt, p0, f);
     } else if (zres) {
         Cell<S, FID, MSD, EXT> gz;
-        ghost_cell(gz, a.ghost, 5);
+        ghost_cell(gz, a.ghost, 5, a.fc);
         add_link<2, +1>(cur, gz, p0, f);
     }
     const int64_t pz = plane * z;
@@ -652,10 +751,13 @@ __device__ __forceinline__ void sweep_tile(const StepArgs &a, const SweepPlan &p
             load_cell(w0, src, F, MU, plane * zm, th.own);
         if (zp >= 0)
             load_cell(w2, src, F, MU, plane * zp, th.own);
+        // the first plane's prv and cur are used at once; nxt is weighed where first used
+        weigh(w0, a.fc);
+        weigh(w1, a.fc);
     }
     if (th.hslot >= 0) {
         if (EXT && th.hghost >= 0)
-            ghost_cell(halo, a.ghost, th.hghost);
+            ghost_cell(halo, a.ghost, th.hghost, a.fc);
         else
             load_cell(halo, src, F, MU, plane * z0, th.halo);
     }

@@ -223,7 +223,7 @@ def test_errors():
             lat.set_reservoir(0, 0, 0.0, 1.0)
         assert e.value.status == N.LPC_ERR_STATE
         for bad, code in ((-INF, N.LPC_ERR_NONFINITE), (np.nan, N.LPC_ERR_NONFINITE),
-                          (2e30, N.LPC_ERR_ARG)):
+                          (2e30, N.LPC_ERR_ARG), (1500.0, N.LPC_ERR_ARG)):
             F = f.F.copy()
             F[1, 2, 3] = bad
             with pytest.raises(N.LpcError) as e:
