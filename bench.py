@@ -12,7 +12,8 @@ Other workloads (--workload): `batch` (512 particles of radius 8-48 in one batch
 against the same particles run one at a time), `film` (2048 x 256 x 256 supercapacitor
 film, closed in x), `serve` (Poisson arrivals of spectrum requests through the
 continuous-batching server), `equilibrate` (the population-only equilibration phase on the
-256^3 particle) and `copy` (plain device copy). Each prints one JSON line.
+256^3 particle), `porous` (the same particle with a solid matrix, link mobility and
+reservoir faces) and `copy` (plain device copy). Each prints one JSON line.
 """
 from __future__ import annotations
 
@@ -273,6 +274,69 @@ def workload_film(args):
     }
 
 
+# ------------------------------------------------------------------- porous particle, reservoirs
+
+def workload_porous(args):
+    """The extended sweep: the 256^3 particle with a quarter of its carbon sites solid
+    (inaccessible), pore-width mobility on every link, and bulk reservoir faces on x
+    (F = 0, rho = 1, magnetised, at 0 ppm) in place of the periodic wrap."""
+    from paper_2603_22553_amd import synth
+    from paper_2603_22553_amd.lattice import Lattice
+    f, mu = synth.porous_particle()
+    precisions = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    res = {}
+    for p in precisions:
+        lat = Lattice(f.shape_xyz, bc=("reservoir", "periodic", "periodic"), precision=p,
+                      n_regions=f.n_regions, max_records=args.steps + args.warmup + 1,
+                      mobility=True)
+        lat.set_fields(f)
+        lat.set_mobility(mu)
+        for side in (0, 1):
+            lat.set_reservoir(0, side, 0.0, 1.0, 1.0)
+        lat.init_state("boltzmann")
+        lat.run(args.warmup)
+        lat.synchronize()
+
+        def work():
+            lat.run(args.steps)
+            return lat.peak_ppm(), lat.diffusion()
+
+        (peak, (D, ratio)), ms = timed(lat.stream, work)
+        mass = lat.moments()[0]
+        plan = lat.describe()
+        lat.close()
+        res[p] = {"ms": ms, "gsu_s": f.n_sites * args.steps / (ms * 1e-3) / 1e9, "peak": peak,
+                  "ratio": [round(float(v), 5) for v in ratio],
+                  "mass_change": float(mass[-1] / mass[0] - 1.0), "plan": plan}
+        print(f"# porous {p}: {res[p]['gsu_s']:.2f} GSU/s", file=sys.stderr, flush=True)
+    out = None
+    for p, r in res.items():
+        ms_step = r["ms"] / args.steps
+        # the mobility field is one more field read per site-update
+        b = bytes_per_site_update(p, ("fid", "msd"), f.n_regions) + (8 if p == "fp64" else 4)
+        ach = f.n_sites * b / (ms_step * 1e-3) / 1e9
+        rl = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+              "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_site_update": b}
+        entry = {"value": round(r["gsu_s"], 4), "unit": "GSU/s", "ms_per_step": round(ms_step, 6),
+                 "dtype": "f64" if p == "fp64" else "f32-storage/f64-sums", "roofline": rl,
+                 "results": {"peak_ppm": round(r["peak"], 4), "D_over_Dbulk": r["ratio"],
+                             "mass_change": r["mass_change"]}}
+        if out is None:
+            out = {"metric": METRIC, "value": entry["value"], "unit": "GSU/s", "n_gpus": 1,
+                   "steps": args.steps, "warmup": args.warmup,
+                   "ms_per_step": entry["ms_per_step"], "higher_is_better": True,
+                   "scaling": "weak", "vs_baseline": None, "dtype": entry["dtype"],
+                   "data": "synthetic",
+                   "config": {"workload": "porous 256^3 particle: 25 % of carbon sites solid, "
+                                          "pore-width link mobility, bulk reservoir faces in x, "
+                                          "Boltzmann start, FID + MSD",
+                              "sites": f.n_sites, "precision": p, "plan": r["plan"]},
+                   "roofline": rl, "results": entry["results"]}
+        else:
+            out[p] = entry
+    return out
+
+
 # ------------------------------------------------------------------- equilibration phase
 
 def workload_equilibrate(args):
@@ -417,7 +481,7 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", choices=["particle", "batch", "film", "serve", "copy",
-                                           "equilibrate"],
+                                           "equilibrate", "porous"],
                     default="particle")
     ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both")
     ap.add_argument("--cpu-steps", type=int, default=20,
@@ -435,7 +499,8 @@ def main():
               "would shard by slabs with one halo exchange per pass; not built).", file=sys.stderr)
         sys.exit(2)
     defaults = {"particle": (50000, 200), "batch": (2000, 20), "film": (1000, 20),
-                "serve": (0, 0), "copy": (20, 1), "equilibrate": (5000, 200)}[args.workload]
+                "serve": (0, 0), "copy": (20, 1), "equilibrate": (5000, 200),
+                "porous": (5000, 100)}[args.workload]
     if args.steps is None:
         args.steps = defaults[0]
     if args.warmup is None:
@@ -445,7 +510,7 @@ def main():
     assert torch.cuda.is_available(), "no GPU"
     fn = {"particle": workload_particle, "batch": workload_batch, "film": workload_film,
           "serve": workload_serve, "copy": workload_copy,
-          "equilibrate": workload_equilibrate}[args.workload]
+          "equilibrate": workload_equilibrate, "porous": workload_porous}[args.workload]
     print(json.dumps(fn(args)), flush=True)
 
 

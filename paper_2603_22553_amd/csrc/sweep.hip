@@ -649,8 +649,11 @@ __device__ __forceinline__ void plane_step(LDS &L, const StepArgs &a, const Tile
     finish_site<S, FID, MSD, EXT, MAXR>(cur, f, theta, r, dst, pz, own, acc);
 }
 
+// At least two resident workgroups per compute unit (two waves per SIMD): every variant
+// fits its registers in the 256 this allows; without the bound the widest one (FP64,
+// extended, FID + moments) takes 257 and drops to one wave per SIMD.
 #ifndef LPC_MIN_WAVES
-#define LPC_MIN_WAVES 1
+#define LPC_MIN_WAVES 2
 #endif
 
 // One step over a TX x TY tile of x-y columns and the workgroup's run of z-planes. Each

@@ -116,6 +116,27 @@ def single_particle_large(seed: int = 1) -> Fields:
     return particle(256, 112, 8.0, (0.7, 2.0), seed)
 
 
+def porous_particle(side: int = 256, radius: float = 112, corr_len: float = 8.0,
+                    solid_fraction: float = 0.25, w_range=(0.7, 2.0), seed: int = 1):
+    """The single particle with a solid matrix and pore-size-dependent mobility.
+
+    The carbon sites whose pore width falls in the lowest `solid_fraction` of the particle
+    become inaccessible (F = +inf): the narrowest pores close first. Mobility is
+    mu = w / w_max over the carbon (confined sites slower) and 1 in the bulk. Returns
+    (Fields, mu).
+    """
+    f = particle(side, radius, corr_len, w_range, seed)
+    inside = f.region == 1
+    rng = np.random.default_rng(seed)
+    g = _standardise(gaussian_random_field(f.F.shape, corr_len, rng), inside)
+    w = width_uniform(g, *w_range)
+    cut = np.quantile(w[inside], solid_fraction)
+    solid = inside & (w <= cut)
+    F = np.where(solid, np.inf, f.F)
+    mu = np.where(inside, np.clip(w / w_range[1], 0.05, 1.0), 1.0)
+    return Fields(np.ascontiguousarray(F), f.delta, f.region, f.n_regions), np.ascontiguousarray(mu)
+
+
 @dataclasses.dataclass
 class ParticleSpec:
     radius: int
