@@ -202,17 +202,29 @@ __global__ __launch_bounds__(kThreads) void k_change_partial(const double *a, co
     }
 }
 
-__global__ void k_change_final(const double *part, int nparts, double *out)
+__global__ __launch_bounds__(kThreads) void k_change_final(const double *part, int nparts,
+                                                           double *out)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0)
-        return;
+    __shared__ double sd[kThreads], sb[kThreads];
     double d = 0.0, m = 0.0;
-    for (int b = 0; b < nparts; ++b) {
+    for (int b = threadIdx.x; b < nparts; b += kThreads) {
         d = fmax(d, part[2 * b]);
         m = fmax(m, part[2 * b + 1]);
     }
-    out[0] = d;
-    out[1] = m;
+    sd[threadIdx.x] = d;
+    sb[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            sd[threadIdx.x] = fmax(sd[threadIdx.x], sd[threadIdx.x + s]);
+            sb[threadIdx.x] = fmax(sb[threadIdx.x], sb[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = sd[0];
+        out[1] = sb[0];
+    }
 }
 
 int grid_for(int64_t n)
@@ -254,7 +266,7 @@ hipError_t launch_max_change(const double *prev, const double *next, int64_t n, 
                              int32_t nparts, double *out, hipStream_t s)
 {
     hipLaunchKernelGGL(k_change_partial, dim3(nparts), dim3(kThreads), 0, s, prev, next, n, part);
-    hipLaunchKernelGGL(k_change_final, dim3(1), dim3(64), 0, s, part, nparts, out);
+    hipLaunchKernelGGL(k_change_final, dim3(1), dim3(kThreads), 0, s, part, nparts, out);
     return hipGetLastError();
 }
 

@@ -750,7 +750,12 @@ lpc_status lpc_equilibrate(lpc_lattice *lat, int64_t max_steps, double tol, int6
         return s;
     SoloTables *t = lat->solo();
     lpc::StepList list{&t->item, t->prefix, 1, lat->L.plan.tx, lat->L.plan.nblocks, 0, 0};
-    double *part = lat->at<double>(lat->L.off_argmax);     // kArgmaxParts x 2 doubles
+    // workgroup maxima in the per-step partial sums (population-only steps discard theirs,
+    // and stream order puts each check between the steps): enough workgroups to stream
+    // both population buffers at full bandwidth
+    constexpr int32_t kChangeParts = 1024;
+    static_assert(kChangeParts * 16 <= kPartialBudget, "change partials exceed the buffer");
+    double *part = lat->partials();
     double *out = lat->scalars() + 8;
     int64_t done = 0;
     double change[2] = {INFINITY, 1.0};
@@ -766,7 +771,7 @@ lpc_status lpc_equilibrate(lpc_lattice *lat, int64_t max_steps, double tol, int6
         }
         done += c;
         LPC_HIP(lpc::launch_max_change(lat->st[1 - lat->cur].rho, lat->st[lat->cur].rho,
-                                       lat->L.n, part, kArgmaxParts, out, lat->stream));
+                                       lat->L.n, part, kChangeParts, out, lat->stream));
         if (lpc_status s = sync(lat))
             return s;
         LPC_HIP(hipMemcpy(change, out, 16, hipMemcpyDeviceToHost));
