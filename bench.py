@@ -13,7 +13,8 @@ against the same particles run one at a time), `film` (2048 x 256 x 256 supercap
 film, closed in x), `serve` (Poisson arrivals of spectrum requests through the
 continuous-batching server), `equilibrate` (the population-only equilibration phase on the
 256^3 particle), `porous` (the same particle with a solid matrix, link mobility and
-reservoir faces) and `copy` (plain device copy). Each prints one JSON line.
+reservoir faces), `supercap` (the monolith / film supercapacitor study at two potentials)
+and `copy` (plain device copy). Each prints one JSON line.
 """
 from __future__ import annotations
 
@@ -70,11 +71,14 @@ def measured_traffic(precision: str):
     return float(m.group(1)) if m else None
 
 
-def roofline(n_sites, precision, ms_step, track=("fid", "msd"), n_regions=2):
+def roofline(n_sites, precision, ms_step, track=("fid", "msd"), n_regions=2, measured=False):
+    """Roofline object of one sweep launch; `traffic` is the counter reading of the 256^3
+    particle workload (measured=True there only; other workloads have not been counted)."""
     b = bytes_per_site_update(precision, track, n_regions)
     ach = n_sites * b / (ms_step * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(precision),
+            "frac": round(ach / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(precision) if measured else None,
             "bytes_per_site_update": b}
 
 
@@ -150,7 +154,7 @@ def workload_particle(args):
                                "particle, FID + MSD recorded every step",
                    "sites": f.n_sites, "regions": f.n_regions, "precision": head,
                    "steps_per_pass": 1, "plan": r["plan"]},
-        "roofline": roofline(f.n_sites, head, ms_step),
+        "roofline": roofline(f.n_sites, head, ms_step, measured=True),
         "results": {"mass_drift": r["mass_drift"], "peak_ppm": round(r["peak_ppm"], 5),
                     "D_over_Dbulk": r["D_over_Dbulk"]},
     }
@@ -159,7 +163,8 @@ def workload_particle(args):
             continue
         ms_p = rr["ms"] / args.steps
         line[p] = {"value": round(rr["gsu_s"], 4), "unit": "GSU/s", "ms_per_step": round(ms_p, 6),
-                   "dtype": "f32-storage/f64-sums", "roofline": roofline(f.n_sites, p, ms_p),
+                   "dtype": "f32-storage/f64-sums",
+                   "roofline": roofline(f.n_sites, p, ms_p, measured=True),
                    "results": {"mass_drift": rr["mass_drift"], "peak_ppm": round(rr["peak_ppm"], 5),
                                "D_over_Dbulk": rr["D_over_Dbulk"]}}
     if args.cpu_steps > 0:
@@ -337,6 +342,36 @@ def workload_porous(args):
     return out
 
 
+# ------------------------------------------------------------------- supercapacitor study
+
+def workload_supercap(args):
+    """The runs of section 4 with synthetic fields: monolith and film supercapacitors
+    (100 x 100 x 300, electrodes of 100 planes, closed in z) at 0 V and 2 V, residence time
+    1 ms, 19F at 282 MHz, mixed path; per part the spectrum peak, D / D_bulk and the uptake
+    relative to 0 V. The value is the site-update rate over the propagation of all runs."""
+    from paper_2603_22553_amd import supercap
+    t = time.perf_counter()
+    runs = supercap.study(steps=args.steps, precision=args.precision if args.precision != "both"
+                          else "mixed")
+    wall = time.perf_counter() - t
+    su = sum(r["sites"] * r["steps"] for r in runs)
+    ms = sum(r["propagate_ms"] for r in runs)
+    prec = args.precision if args.precision != "both" else "mixed"
+    ms_step = ms / sum(r["steps"] for r in runs)
+    table = [{"kind": r["kind"], "potential_v": r["potential_v"],
+              "parts": {k: {kk: round(vv, 5) for kk, vv in v.items()} for k, v in r["parts"].items()}}
+             for r in runs]
+    return {"metric": METRIC, "value": round(su / (ms * 1e-3) / 1e9, 4), "unit": "GSU/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": 0, "ms_per_step": round(ms_step, 6),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64" if prec == "fp64" else "f32-storage/f64-sums", "data": "synthetic",
+            "config": {"workload": "supercapacitor study: monolith and film, 0 V and 2 V, "
+                                   "100x100x300, closed in z, tau 1 ms, 282 MHz, FID + MSD",
+                       "runs": len(runs), "sites": runs[0]["sites"], "precision": prec},
+            "roofline": roofline(runs[0]["sites"], prec, ms_step, n_regions=3),
+            "results": {"table": table, "wall_s_including_setup": round(wall, 1)}}
+
+
 # ------------------------------------------------------------------- equilibration phase
 
 def workload_equilibrate(args):
@@ -481,7 +516,7 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", choices=["particle", "batch", "film", "serve", "copy",
-                                           "equilibrate", "porous"],
+                                           "equilibrate", "porous", "supercap"],
                     default="particle")
     ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both")
     ap.add_argument("--cpu-steps", type=int, default=20,
@@ -500,7 +535,7 @@ def main():
         sys.exit(2)
     defaults = {"particle": (50000, 200), "batch": (2000, 20), "film": (1000, 20),
                 "serve": (0, 0), "copy": (20, 1), "equilibrate": (5000, 200),
-                "porous": (5000, 100)}[args.workload]
+                "porous": (5000, 100), "supercap": (50000, 0)}[args.workload]
     if args.steps is None:
         args.steps = defaults[0]
     if args.warmup is None:
@@ -510,7 +545,8 @@ def main():
     assert torch.cuda.is_available(), "no GPU"
     fn = {"particle": workload_particle, "batch": workload_batch, "film": workload_film,
           "serve": workload_serve, "copy": workload_copy,
-          "equilibrate": workload_equilibrate, "porous": workload_porous}[args.workload]
+          "equilibrate": workload_equilibrate, "porous": workload_porous,
+          "supercap": workload_supercap}[args.workload]
     print(json.dumps(fn(args)), flush=True)
 
 

@@ -214,6 +214,14 @@ lpc_status lpc_diffusion(lpc_lattice *lat, double *D_m2_s, double *ratio);
  * units^2); needs LPC_TRACK_MSD and N >= 2. */
 lpc_status lpc_read_vacf(lpc_lattice *lat, double *vacf_xyz, int64_t cap, int64_t *len);
 
+/* Per-region sums over the current state, 7 per region r < n_regions: the population and
+ * the first and second displacement moments along x, y, z (moment propagation, section
+ * 2.2): sums[7 r + q], q = 0 rho, 1..3 M1_x..z, 4..6 M2_x..z. M2 / rho of a region is the
+ * mean-square displacement of the particles now in it, from which per-part diffusion
+ * coefficients follow (section 4, Table 1). Needs LPC_TRACK_MSD; cap >= 7 n_regions.
+ * Deterministic (fixed summation order). Synchronous. */
+lpc_status lpc_region_moments(lpc_lattice *lat, double *sums, int64_t cap);
+
 /* Populations of the current state summed over the planes perpendicular to `axis`
  * (0 x, 1 y, 2 z): n[axis] values (the uptake profile across a film along x). */
 lpc_status lpc_uptake_profile(lpc_lattice *lat, int32_t axis, double *profile, int64_t cap);

@@ -92,6 +92,7 @@ SIGNATURES = {
     "lpc_uptake_profile": [_P, _I32, _P, _I64],
     "lpc_equilibrate": [_P, _I64, ctypes.c_double, _I64, _PI64, ctypes.POINTER(ctypes.c_double)],
     "lpc_read_vacf": [_P, _P, _I64, _PI64],
+    "lpc_region_moments": [_P, _P, _I64],
     "lpc_batch_query_footprint": [_I32, _PSZ],
     "lpc_batch_create": [_P, _I32, _P, _SZ, _P, ctypes.POINTER(_P)],
     "lpc_batch_destroy": [_P],

@@ -227,6 +227,79 @@ __global__ __launch_bounds__(kThreads) void k_change_final(const double *part, i
     }
 }
 
+// Per-region sums of rho, M1_a and M2_a (7 values per region: rho, M1 x y z, M2 x y z)
+// over the state: workgroup partials in part[k * nparts + b], k = 7 r + q, for a
+// fixed-order finalisation. Butterflies inside each wave, waves in index order.
+template <typename S, int MAXR>
+__global__ __launch_bounds__(kThreads) void k_region_sums(const double *rho, const S *m1x,
+                                                          const S *m1y, const S *m1z,
+                                                          const S *m2x, const S *m2y,
+                                                          const S *m2z, const uint8_t *region,
+                                                          int64_t n, int R, double *part)
+{
+    __shared__ double lds[(kThreads / 64) * 7 * MAXR];
+    double acc[MAXR][7];
+#pragma unroll
+    for (int k = 0; k < MAXR; ++k)
+#pragma unroll
+        for (int q = 0; q < 7; ++q)
+            acc[k][q] = 0.0;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kThreads) {
+        const int r = MAXR == 1 ? 0 : region[i];
+        const double v[7] = {rho[i],
+                             static_cast<double>(m1x[i]), static_cast<double>(m1y[i]),
+                             static_cast<double>(m1z[i]), static_cast<double>(m2x[i]),
+                             static_cast<double>(m2y[i]), static_cast<double>(m2z[i])};
+#pragma unroll
+        for (int k = 0; k < MAXR; ++k)
+#pragma unroll
+            for (int q = 0; q < 7; ++q)
+                acc[k][q] += k == r ? v[q] : 0.0;
+    }
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+#pragma unroll
+    for (int k = 0; k < MAXR; ++k)
+#pragma unroll
+        for (int q = 0; q < 7; ++q) {
+            const double t = warp_sum(acc[k][q]);
+            if (lane == 0)
+                lds[wave * 7 * MAXR + 7 * k + q] = t;
+        }
+    __syncthreads();
+    if (static_cast<int>(threadIdx.x) < 7 * R) {
+        double t = 0.0;
+        for (int w = 0; w < kThreads / 64; ++w)
+            t += lds[w * 7 * MAXR + threadIdx.x];
+        part[static_cast<int64_t>(threadIdx.x) * gridDim.x + blockIdx.x] = t;
+    }
+}
+
+template <typename S>
+hipError_t region_sums_typed(const StateView &st, const uint8_t *region, int64_t n, int32_t R,
+                             double *part, int32_t nparts, hipStream_t s)
+{
+    const S *m1[3], *m2[3];
+    for (int a = 0; a < 3; ++a) {
+        m1[a] = static_cast<const S *>(st.m1[a]);
+        m2[a] = static_cast<const S *>(st.m2[a]);
+    }
+    const dim3 grid(nparts), block(kThreads);
+    if (R == 1)
+        hipLaunchKernelGGL((k_region_sums<S, 1>), grid, block, 0, s, st.rho, m1[0], m1[1], m1[2],
+                           m2[0], m2[1], m2[2], region, n, R, part);
+    else if (R == 2)
+        hipLaunchKernelGGL((k_region_sums<S, 2>), grid, block, 0, s, st.rho, m1[0], m1[1], m1[2],
+                           m2[0], m2[1], m2[2], region, n, R, part);
+    else if (R <= 4)
+        hipLaunchKernelGGL((k_region_sums<S, 4>), grid, block, 0, s, st.rho, m1[0], m1[1], m1[2],
+                           m2[0], m2[1], m2[2], region, n, R, part);
+    else
+        hipLaunchKernelGGL((k_region_sums<S, 8>), grid, block, 0, s, st.rho, m1[0], m1[1], m1[2],
+                           m2[0], m2[1], m2[2], region, n, R, part);
+    return hipGetLastError();
+}
+
 int grid_for(int64_t n)
 {
     int64_t g = (n + kThreads - 1) / kThreads;
@@ -268,6 +341,13 @@ hipError_t launch_max_change(const double *prev, const double *next, int64_t n, 
     hipLaunchKernelGGL(k_change_partial, dim3(nparts), dim3(kThreads), 0, s, prev, next, n, part);
     hipLaunchKernelGGL(k_change_final, dim3(1), dim3(kThreads), 0, s, part, nparts, out);
     return hipGetLastError();
+}
+
+hipError_t launch_region_sums(int32_t precision, const StateView &st, const uint8_t *region,
+                              int64_t n, int32_t R, double *part, int32_t nparts, hipStream_t s)
+{
+    return precision == 0 ? region_sums_typed<double>(st, region, n, R, part, nparts, s)
+                          : region_sums_typed<float>(st, region, n, R, part, nparts, s);
 }
 
 hipError_t launch_profile(const double *rho, const Geometry &g, int32_t axis, double *profile,

@@ -75,7 +75,7 @@ struct Layout {
     int64_t staging = 0;
     size_t off_F = 0, off_theta = 0, off_region = 0, off_mu = 0, off_ghost = 0, off_partials = 0,
            off_records = 0, off_staging = 0, off_scalars = 0, off_fft = 0, off_argmax = 0,
-           off_profile = 0, off_list = 0;
+           off_profile = 0, off_list = 0, off_regsum = 0;
     int64_t fft_max = 0;
     size_t off_rho[2] = {0, 0}, off_re[2] = {0, 0}, off_im[2] = {0, 0};
     size_t off_m1[2][3] = {}, off_m2[2][3] = {};
@@ -201,6 +201,7 @@ Layout plan_layout(const lpc_config &c)
     L.off_argmax = take(kArgmaxParts * 16 + 64);
     L.off_profile = take(size_t(std::max(c.n[0], std::max(c.n[1], c.n[2]))) * 8);
     L.off_list = take(sizeof(SoloTables));
+    L.off_regsum = take(7 * LPC_MAX_REGIONS * 8);
     L.total = o;
     set_chunk(L);
     return L;
@@ -1258,6 +1259,35 @@ lpc_status lpc_read_vacf(lpc_lattice *lat, double *vacf_xyz, int64_t cap, int64_
             vacf_xyz[3 * tau + a] = 0.5 * ((msd(tau + 1, a) - msd(tau, a)) - (msd(tau, a) - msd(tau - 1, a)));
     }
     *len = N;
+    return ok();
+}
+
+lpc_status lpc_region_moments(lpc_lattice *lat, double *sums, int64_t cap)
+{
+    if (!lat || !sums)
+        return fail(LPC_ERR_ARG, "NULL argument");
+    if (!msd_of(lat->cfg))
+        return fail(LPC_ERR_STATE, "displacement moments are not tracked");
+    if (!lat->initialized)
+        return fail(LPC_ERR_STATE, "state not initialised");
+    const int32_t R = lat->cfg.n_regions;
+    if (cap < 7 * R)
+        return fail(LPC_ERR_OOM, "region sums have %d values, buffer holds %lld", 7 * R,
+                    (long long)cap);
+    if (lpc_status s = use_device(lat))
+        return s;
+    // workgroup partials in the per-step partial buffer: queued after the last finalisation
+    constexpr int32_t kParts = 1024;
+    static_assert(int64_t(kParts) * 7 * LPC_MAX_REGIONS * 8 <= kPartialBudget,
+                  "region partials exceed the buffer");
+    double *dev = lat->at<double>(lat->L.off_regsum);
+    LPC_HIP(lpc::launch_region_sums(lat->cfg.precision, lat->st[lat->cur],
+                                    lat->at<uint8_t>(lat->L.off_region), lat->L.n, R,
+                                    lat->partials(), kParts, lat->stream));
+    LPC_HIP(lpc::launch_finalize(lat->partials(), kParts, 7 * R, 1, dev, lat->stream));
+    if (lpc_status s = sync(lat))
+        return s;
+    LPC_HIP(hipMemcpy(sums, dev, size_t(7 * R) * 8, hipMemcpyDeviceToHost));
     return ok();
 }
 

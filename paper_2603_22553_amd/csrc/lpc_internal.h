@@ -144,6 +144,10 @@ hipError_t launch_argmax(const double *v, int64_t n, double *pval, int64_t *pidx
 // doubles in part).
 hipError_t launch_max_change(const double *prev, const double *next, int64_t n, double *part,
                              int32_t nparts, double *out, hipStream_t s);
+// Workgroup partials part[k * nparts + b] of the per-region sums k = 7 r + q of rho, M1_a,
+// M2_a (q = 0: rho; 1..3: M1 x y z; 4..6: M2 x y z); finalised like record partials.
+hipError_t launch_region_sums(int32_t precision, const StateView &st, const uint8_t *region,
+                              int64_t n, int32_t R, double *part, int32_t nparts, hipStream_t s);
 // Population summed over the planes perpendicular to `axis`.
 hipError_t launch_profile(const double *rho, const Geometry &g, int32_t axis, double *profile,
                           hipStream_t s);

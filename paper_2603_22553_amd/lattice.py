@@ -284,6 +284,13 @@ class Lattice:
         N.call("lpc_read_vacf", self.handle, _ptr(out), n, ctypes.byref(got))
         return out[:got.value]
 
+    def region_moments(self) -> np.ndarray:
+        """(n_regions, 7): per region the population and the M1, M2 sums along x, y, z of
+        the current state."""
+        out = np.empty(7 * self.n_regions)
+        N.call("lpc_region_moments", self.handle, _ptr(out), out.size)
+        return out.reshape(self.n_regions, 7)
+
     def kohn_diffusion(self, lag=None) -> np.ndarray:
         """Eq. (4) truncated at `lag` (default: all recorded lags), m^2/s per axis."""
         C = self.vacf()

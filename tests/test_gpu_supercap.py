@@ -1,0 +1,80 @@
+"""Per-region moment sums and the supercapacitor workflow (section 4) on the GPU, against
+the oracle."""
+import numpy as np
+import pytest
+
+from paper_2603_22553_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle_region_sums(res, region, R):
+    """Region sums of rho, M1 xyz, M2 xyz of an oracle state (plain numpy sums)."""
+    n = res.rho.size
+    reg = region.reshape(-1)
+    out = np.zeros((R, 7))
+    for r in range(R):
+        sel = reg == r
+        out[r, 0] = res.rho[sel].sum()
+        for a in range(3):
+            out[r, 1 + a] = res.M1[a * n:(a + 1) * n][sel].sum()
+            out[r, 4 + a] = res.M2[a * n:(a + 1) * n][sel].sum()
+    return out
+
+
+@pytest.mark.parametrize("precision,R,tol", [("fp64", 3, 1e-10), ("mixed", 8, 1e-5),
+                                             ("fp64", 1, 1e-10)])
+def test_region_moments_against_oracle(oracle, precision, R, tol):
+    from paper_2603_22553_amd.lattice import Lattice
+    f = synth.random_fields((37, 22, 29), seed=111 + R, n_regions=R)
+    with Lattice(f.shape_xyz, bc=("periodic", "closed", "periodic"), precision=precision,
+                 n_regions=R, max_records=121) as lat:
+        lat.set_fields(f)
+        lat.init_state("boltzmann")
+        lat.run(120)
+        got = lat.region_moments()
+    ref = oracle.run(f.F, f.delta, f.region, R, 120, bc=(0, 1, 0), init="boltzmann")
+    want = oracle_region_sums(ref, f.region, R)
+    scale = np.max(np.abs(want), axis=0)
+    scale[1:4] = np.maximum(scale[1:4], scale[4:7])     # first moments may vanish
+    assert np.all(np.abs(got - want) <= tol * scale)
+
+
+def test_region_moments_needs_moments():
+    from paper_2603_22553_amd import _native as N
+    from paper_2603_22553_amd.lattice import Lattice
+    with Lattice((8, 8, 8), track=("fid",), max_records=2) as lat:
+        lat.init_state()
+        with pytest.raises(N.LpcError) as e:
+            lat.region_moments()
+        assert e.value.status == N.LPC_ERR_STATE
+
+
+@pytest.mark.parametrize("kind", ["monolith", "film"])
+def test_workflow_against_oracle(oracle, kind):
+    """One run of the workflow on a small supercapacitor (FP64): per-part peaks, D / D_bulk
+    and uptakes equal those computed the same way from oracle runs."""
+    from paper_2603_22553_amd import supercap as S
+    from paper_2603_22553_amd.lattice import p_hop_from_residence_time
+    sysm = S.system(kind, 2.0, shape_xyz=(16, 16, 48), electrode=16, radius=3)
+    steps, tau = 400, 0.2e-3
+    got = S.run(sysm, steps, tau, precision="fp64")
+    f = sysm.fields
+    p0 = p_hop_from_residence_time(tau, 5e-6)
+    kw = dict(bc=(0, 0, 1), p0=p0, dt=5e-6, nu0=282e6)
+    a = oracle.run(f.F, f.delta, f.region, 3, steps // 2, init="boltzmann", **kw)
+    b = oracle.run(f.F, f.delta, f.region, 3, steps - steps // 2,
+                   state=(a.rho, a.re, a.im, a.M1, a.M2), **kw)
+    ratio = S.part_diffusion(oracle_region_sums(a, f.region, 3), oracle_region_sums(b, f.region, 3),
+                             steps - steps // 2, p0)
+    for r, name in S.PARTS.items():
+        part = got["parts"][name]
+        G = np.concatenate([a.fid(r), b.fid(r)[1:]])
+        assert abs(part["peak_ppm"] - oracle.peak_ppm(G, 5e-6, 282e6)) <= 0.01
+        assert abs(part["D_over_Dbulk"] - ratio[r]) <= 1e-9 * abs(ratio[r])
+        assert abs(part["uptake"] - a.uptake()[0, r]) <= 1e-12 * a.uptake()[0].sum()
+    # the positive electrode takes up anions at 2 V, the negative one gives them away
+    base = S.run(S.system(kind, 0.0, shape_xyz=(16, 16, 48), electrode=16, radius=3), 10, tau,
+                 precision="fp64")
+    assert got["parts"]["electrode +"]["uptake"] > base["parts"]["electrode +"]["uptake"]
+    assert got["parts"]["electrode -"]["uptake"] < base["parts"]["electrode -"]["uptake"]
