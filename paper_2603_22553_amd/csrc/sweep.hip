@@ -568,9 +568,9 @@ struct TileThread {
     bool act, has_xm, has_xp, has_ym, has_yp;
 };
 
-// One z-plane of the tile: stage it in LDS buffer `L` (own site + halo site), wait for the
-// whole tile, prefetch plane z+2 (own column) into `nx2` and the halo of plane z+1 into
-// `halo`, then update every site of the plane from LDS (x, y) and registers (z).
+// One z-plane of the tile: stage it in LDS buffer `L` (own site + halo site), prefetch
+// plane z+2 (own column) into `nx2` and the halo of plane z+1 into `halo`, wait for the
+// whole tile, then update every site of the plane from LDS (x, y) and registers (z).
 template <typename S, bool FID, bool MSD, bool EXT, int MAXR, int TX, typename LDS>
 __device__ __forceinline__ void plane_step(LDS &L, const StepArgs &a, const TileThread &th,
                                            const View<S> &src, const View<S> &dst, const S *F,
@@ -591,12 +591,13 @@ __device__ __forceinline__ void plane_step(LDS &L, const StepArgs &a, const Tile
             weigh(halo, a.fc);
         L.put(th.hslot, halo);
     }
-    __syncthreads();
     // The column offsets are re-materialised every plane so that base + offset is not
     // hoisted into per-array 64-bit vector registers: each load then takes the plane's
     // scalar base plus one 32-bit vector offset.
     Off own = th.own, hal = th.halo;
     asm volatile("" : "+v"(own.b8), "+v"(own.bs), "+v"(own.b1), "+v"(hal.b8), "+v"(hal.bs));
+    // The prefetches go out before the barrier (their registers are free once the puts
+    // have read them), so the wait at the barrier also covers their latency.
     if (z + 1 < z1) {
         // z + 2 <= nz here, so a periodic wrap lands on plane 0
         const int zn = z + 2 < g.nz ? z + 2 : (zper ? 0 : -1);
@@ -605,6 +606,7 @@ __device__ __forceinline__ void plane_step(LDS &L, const StepArgs &a, const Tile
         if (th.hslot >= 0 && (!EXT || th.hghost < 0))
             load_cell(halo, src, F, MU, plane * (z + 1), hal);
     }
+    __syncthreads();
     if (!th.act)
         return;
     const S p0 = static_cast<S>(a.p0);
