@@ -25,7 +25,9 @@ So the workflow reproduces the shape of the study (which quantities, per which p
 they are compared), not its numbers.
 
 Per run: Boltzmann start (Eq. (2); the closed system's exact equilibrium, so no
-equilibration is needed), then propagation with the FID and the displacement moments.
+equilibration is needed), then propagation with the FID and the displacement moments. The
+systems of a study are stepped together as one batch: a 100 x 100 x 300 lattice alone
+cannot fill the GPU.
 Per part it reports:
 
 * the position of the spectrum's main peak (Eq. (9)) of the part's FID;
@@ -122,49 +124,76 @@ def part_diffusion(mom_a, mom_b, steps_between, p_hop):
     return (slope[:, :2].mean(axis=1)) / (2.0 * p_hop)
 
 
+def run_batch(systems, steps: int = 50000, tau_s: float = 1e-3, dt_s: float = 5e-6,
+              larmor_hz: float = 282e6, precision: str = "mixed", spacing_m: float = 0.5e-9):
+    """Propagation runs of several supercapacitors on the GPU, stepped together as one
+    batch (one launch per step covers every lattice, each ending bit for bit as if run
+    alone); returns per-part results per system and the batch's propagation time."""
+    import torch
+    from .lattice import Batch, Lattice, p_hop_from_residence_time
+    p_hop = p_hop_from_residence_time(tau_s, dt_s)
+    half = steps // 2
+    lats = []
+    try:
+        for sysm in systems:
+            f = sysm.fields
+            lat = Lattice(f.shape_xyz, bc=("periodic", "periodic", "closed"),
+                          precision=precision, n_regions=3, p_hop=p_hop, dt_s=dt_s,
+                          larmor_hz=larmor_hz, spacing_m=spacing_m, max_records=steps + 1)
+            lats.append(lat)
+            lat.set_fields(f)
+            lat.init_state("boltzmann")
+        uptake = [lat.region_moments()[:, 0].copy() for lat in lats]
+        batch = Batch(lats)
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(batch.stream)
+        batch.run(half)
+        mom_a = [lat.region_moments() for lat in lats]
+        batch.run(steps - half)
+        t1.record(batch.stream)
+        mom_b = [lat.region_moments() for lat in lats]
+        t1.synchronize()
+        ms = t0.elapsed_time(t1)
+        batch.close()
+        out = []
+        for sysm, lat, up, ma, mb in zip(systems, lats, uptake, mom_a, mom_b):
+            peaks = [lat.peak_ppm(r) for r in range(3)]
+            lat.check()
+            ratio = part_diffusion(ma, mb, steps - half, p_hop)
+            out.append({"kind": sysm.kind, "potential_v": sysm.potential_v, "tau_s": tau_s,
+                        "p_hop": p_hop, "steps": steps, "sites": sysm.fields.n_sites,
+                        "parts": {PARTS[r]: {"peak_ppm": float(peaks[r]),
+                                             "D_over_Dbulk": float(ratio[r]),
+                                             "uptake": float(up[r])} for r in range(3)}})
+        return out, ms
+    finally:
+        for lat in lats:
+            lat.close()
+
+
 def run(sysm: System, steps: int = 50000, tau_s: float = 1e-3, dt_s: float = 5e-6,
         larmor_hz: float = 282e6, precision: str = "mixed", spacing_m: float = 0.5e-9):
     """One propagation run of a supercapacitor on the GPU; returns per-part results."""
-    import torch
-    from .lattice import Lattice, p_hop_from_residence_time
-    f = sysm.fields
-    p_hop = p_hop_from_residence_time(tau_s, dt_s)
-    half = steps // 2
-    with Lattice(f.shape_xyz, bc=("periodic", "periodic", "closed"), precision=precision,
-                 n_regions=3, p_hop=p_hop, dt_s=dt_s, larmor_hz=larmor_hz,
-                 spacing_m=spacing_m, max_records=steps + 1) as lat:
-        lat.set_fields(f)
-        lat.init_state("boltzmann")
-        uptake = lat.region_moments()[:, 0].copy()
-        t0 = torch.cuda.Event(enable_timing=True)
-        t1 = torch.cuda.Event(enable_timing=True)
-        t0.record(lat.stream)
-        lat.run(half)
-        mom_a = lat.region_moments()
-        lat.run(steps - half)
-        t1.record(lat.stream)
-        mom_b = lat.region_moments()
-        peaks = [lat.peak_ppm(r) for r in range(3)]
-        lat.check()
-        ms = t0.elapsed_time(t1)
-    ratio = part_diffusion(mom_a, mom_b, steps - half, p_hop)
-    return {"kind": sysm.kind, "potential_v": sysm.potential_v, "tau_s": tau_s,
-            "p_hop": p_hop, "steps": steps, "sites": f.n_sites, "propagate_ms": ms,
-            "parts": {PARTS[r]: {"peak_ppm": float(peaks[r]), "D_over_Dbulk": float(ratio[r]),
-                                 "uptake": float(uptake[r])} for r in range(3)}}
+    out, ms = run_batch([sysm], steps, tau_s, dt_s, larmor_hz, precision, spacing_m)
+    out[0]["propagate_ms"] = ms
+    return out[0]
 
 
 def study(kinds=("monolith", "film"), potentials=(0.0, 2.0), taus=(1e-3,), steps: int = 50000,
           shape_xyz=(100, 100, 300), electrode: int = 100, precision: str = "mixed",
           seed: int = 5000, **system_kw):
-    """The runs of section 4 for every (structure, potential, residence time), plus the
-    normalised electrode uptake rho_tot(V) / rho_tot(0 V) of Fig. 8b per structure."""
-    runs = []
-    for kind in kinds:
-        for v in potentials:
-            sysm = system(kind, v, shape_xyz, electrode, seed=seed, **system_kw)
-            for tau in taus:
-                runs.append(run(sysm, steps, tau, precision=precision))
+    """The runs of section 4 for every (structure, potential, residence time), the systems
+    of one residence time stepped as one batch, plus the normalised electrode uptake
+    rho_tot(V) / rho_tot(0 V) of Fig. 8b per structure. Returns (runs, propagation ms per
+    batch)."""
+    systems = [system(kind, v, shape_xyz, electrode, seed=seed, **system_kw)
+               for kind in kinds for v in potentials]
+    runs, times = [], []
+    for tau in taus:
+        out, ms = run_batch(systems, steps, tau, precision=precision)
+        runs.extend(out)
+        times.append(ms)
     base = {r["kind"]: r for r in runs if r["potential_v"] == 0.0 and r["tau_s"] == taus[0]}
     for r in runs:
         b = base.get(r["kind"])
@@ -173,4 +202,4 @@ def study(kinds=("monolith", "film"), potentials=(0.0, 2.0), taus=(1e-3,), steps
         for part in ("electrode -", "electrode +"):
             r["parts"][part]["uptake_vs_0V"] = (r["parts"][part]["uptake"]
                                                 / b["parts"][part]["uptake"])
-    return runs
+    return runs, times

@@ -78,3 +78,16 @@ def test_workflow_against_oracle(oracle, kind):
                  precision="fp64")
     assert got["parts"]["electrode +"]["uptake"] > base["parts"]["electrode +"]["uptake"]
     assert got["parts"]["electrode -"]["uptake"] < base["parts"]["electrode -"]["uptake"]
+
+
+def test_batched_study_equals_solo_runs():
+    """The study steps its systems as one batch; every number equals a run alone."""
+    from paper_2603_22553_amd import supercap as S
+    kw = dict(shape_xyz=(16, 16, 48), electrode=16, radius=3)
+    runs, times = S.study(steps=120, precision="fp64", **kw)
+    assert len(runs) == 4 and len(times) == 1 and times[0] > 0
+    for r in runs:
+        alone = S.run(S.system(r["kind"], r["potential_v"], **kw), 120, precision="fp64")
+        for part, vals in r["parts"].items():
+            for key in ("peak_ppm", "D_over_Dbulk", "uptake"):
+                assert vals[key] == alone["parts"][part][key], (r["kind"], part, key)
