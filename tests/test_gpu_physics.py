@@ -282,3 +282,18 @@ def test_extended_checkpoint_restart_bitwise():
         b.run(60)
         assert np.array_equal(b.records(), want[0])
         assert np.array_equal(b.population(), want[1])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_porous_full_size(oracle, precision):
+    """The porous 256^3 workload (a quarter of the carbon solid, pore-width mobility, bulk
+    reservoir faces in x) at full size in the benchmark's launch configuration, over a short
+    prefix the oracle finishes in seconds."""
+    f, mu = synth.porous_particle()
+    faces = {(0, 0): (0.0, 1.0, 1.0, 0.0), (0, 1): (0.0, 1.0, 1.0, 0.0)}
+    steps = 3
+    bc = (RES, PER, PER)
+    rec, rho, m = gpu(f.shape_xyz, f, f.F, mu, faces, bc, steps, precision, init="boltzmann")
+    ref = oracle.run(f.F, f.delta, f.region, f.n_regions, steps, bc=bc, mobility=mu,
+                     reservoir=faces, init="boltzmann")
+    check(f"porous 256^3 {precision}", rec, rho, m, ref, f.n_regions, precision)
