@@ -27,8 +27,10 @@ def oracle():
 
 
 def parse_value(s):
-    """'a/b', 'ln2'-style and decimal strings of the golden fixtures -> float."""
+    """'a/b', 'ln2'-style, 'inf' and decimal strings of the golden fixtures -> float."""
     s = str(s).strip()
+    if s == "inf":
+        return math.inf
     if s.startswith("ln"):
         return math.log(float(s[2:]))
     return float(Fraction(s))

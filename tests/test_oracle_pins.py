@@ -27,9 +27,17 @@ def _flat(a):
 
 @pytest.mark.parametrize("case", load_golden("hand_cases.json")["cases"], ids=lambda c: c["name"])
 def test_hand_cases(oracle, case):
-    """Tiny lattices stepped by hand (Eqs. (1), (5), (7), (13); moment propagation)."""
+    """Tiny lattices stepped by hand (Eqs. (1), (5), (7), (13); moment propagation; the
+    Dirichlet ghost sites of section 3.2)."""
     nx, ny, nz = case["shape_xyz"]
-    bc = tuple(PER if b == "periodic" else CLO for b in case["bc"])
+    bc = tuple({"periodic": PER, "closed": CLO, "reservoir": 2}[b] for b in case["bc"])
+    reservoir = {tuple(int(v) for v in k.split(",")): tuple(parse_value(x) for x in vals)
+                 for k, vals in case.get("reservoir", {}).items()} or None
+    mobility = (np.array([parse_value(v) for v in case["mobility"]]).reshape(nz, ny, nx)
+                if "mobility" in case else None)
+    init = case.get("init", "uniform")
+    if not isinstance(init, str):
+        init = np.array([parse_value(v) for v in init]).reshape(nz, ny, nx)
     F = np.array([parse_value(v) for v in case["F"]]).reshape(nz, ny, nx)
     delta = np.array([parse_value(v) for v in case["delta_ppm"]]).reshape(nz, ny, nx)
     region = np.array(case["region"], dtype=np.uint8).reshape(nz, ny, nx)
@@ -37,7 +45,8 @@ def test_hand_cases(oracle, case):
     last = max(s["n"] for s in case["steps"])
     for step in case["steps"]:
         res = oracle.run(F, delta, region, R, step["n"], bc=bc, p0=parse_value(case["p0"]),
-                         dt=case["dt"], nu0=case["nu0"])
+                         dt=case["dt"], nu0=case["nu0"], init=init, reservoir=reservoir,
+                         mobility=mobility)
         want = {k: np.array([parse_value(v) for v in step[k]]) for k in
                 ("rho", "m_re", "m_im", "S1", "S2")}
         np.testing.assert_allclose(res.rho, want["rho"], rtol=0, atol=1e-15)
