@@ -25,7 +25,6 @@ struct Geometry {
 // and a run of zc planes. Blocks are renumbered so that each XCD gets a contiguous
 // range of tiles (hardware dispatch is round-robin over the 8 XCDs).
 struct SweepPlan {
-    int32_t kernel;      // 0 = direct (cache-read neighbours), 1 = z-march with LDS tiles
     int32_t tx, ty, zc;
     int32_t gx, gy, gz;
     int64_t nblocks;

@@ -1113,7 +1113,6 @@ int64_t max_sweep_blocks(const Geometry &g)
 SweepPlan make_plan(const Geometry &g, int32_t blocks_per_cu, int32_t cus, int32_t tile_x)
 {
     SweepPlan p{};
-    p.kernel = 1;
     p.tx = tile_x == 64 || tile_x == 32 || tile_x == 16 ? tile_x : tile_width(g.nx);
     p.ty = kThreads / p.tx;
     p.gx = (g.nx + p.tx - 1) / p.tx;
