@@ -116,7 +116,8 @@ def run_particle(f, precision, steps, warmup, track=("fid", "msd")):
     mass = lat.moments()[0]
     out = {"ms": ms, "gsu_s": f.n_sites * steps / (ms * 1e-3) / 1e9,
            "mass_drift": float(abs(mass[-1] / mass[0] - 1.0)), "peak_ppm": peak,
-           "D_over_Dbulk": [round(float(v), 6) for v in ratio], "plan": lat.describe()}
+           "D_over_Dbulk": [round(float(v), 6) for v in ratio], "D": D, "plan": lat.describe(),
+           "fid": lat.fid(), "uptake": lat.uptake()[-1]}
     lat.close()
     return out
 
@@ -167,6 +168,17 @@ def workload_particle(args):
                    "roofline": roofline(f.n_sites, p, ms_p, measured=True),
                    "results": {"mass_drift": rr["mass_drift"], "peak_ppm": round(rr["peak_ppm"], 5),
                                "D_over_Dbulk": rr["D_over_Dbulk"]}}
+    if "fp64" in res and "mixed" in res:
+        # the FP32-storage path against the FP64 path over the whole run (the FP64 path itself
+        # is held to the oracle at 1e-10 by the parity tests)
+        import numpy as np
+        a, m = res["fp64"], res["mixed"]
+        line["precision_comparison"] = {
+            "fid_rel_l2": float(np.linalg.norm(m["fid"] - a["fid"]) / np.linalg.norm(a["fid"])),
+            "uptake_max_rel": float(np.max(np.abs(m["uptake"] - a["uptake"]) / np.abs(a["uptake"]))),
+            "peak_ppm_diff": float(abs(m["peak_ppm"] - a["peak_ppm"])),
+            "D_max_rel": float(np.max(np.abs(np.asarray(m["D"]) - a["D"]) / np.abs(a["D"]))),
+            "steps": args.steps + args.warmup}
     if args.cpu_steps > 0:
         line["cpu_baseline"] = cpu_baseline(f, args.cpu_steps)
     return line
@@ -470,15 +482,22 @@ def workload_serve(args):
                   "gsu_s": round(su_alone / alone_s / 1e9, 3), "bitwise_equal_to_served": True},
     }
     if args.serve_oracle > 0:
+        # a 1 % sample of the served jobs against the oracle, over a prefix of each job's
+        # steps that the oracle finishes in seconds (the served FID rows of that prefix are the
+        # same records)
         from oracle import oracle
         sampled = sorted(jobs[::100], key=lambda j: j.n_sites * j.n_steps)[:args.serve_oracle]
         errs = []
         for j in sampled:
             f = j.fields
-            o = oracle.run(f.F, f.delta, f.region, f.n_regions, j.n_steps, moments=False)
-            errs.append(float(np.linalg.norm(j.result["fid"] - o.fid()) / np.linalg.norm(o.fid())))
+            n = min(j.n_steps, args.serve_oracle_steps)
+            o = oracle.run(f.F, f.delta, f.region, f.n_regions, n, moments=False)
+            g = j.result["fid"][:n + 1]
+            errs.append(float(np.linalg.norm(g - o.fid()) / np.linalg.norm(o.fid())))
         out["oracle_fid_rel_l2_max"] = max(errs)
-        out["oracle_sample"] = [j.job_id for j in sampled]
+        out["oracle_sample"] = {"jobs": [j.job_id for j in sampled],
+                                "steps_compared": [min(j.n_steps, args.serve_oracle_steps)
+                                                   for j in sampled]}
     return out
 
 
@@ -526,7 +545,10 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-alone", type=int, default=20)
-    ap.add_argument("--serve-oracle", type=int, default=0)
+    ap.add_argument("--serve-oracle", type=int, default=1,
+                    help="served jobs compared with the oracle (every 100th job, cheapest first)")
+    ap.add_argument("--serve-oracle-steps", type=int, default=1000,
+                    help="step prefix of a sampled job that the oracle recomputes")
     ap.add_argument("--tick-steps", type=int, default=2000)
     ap.add_argument("--check-every", type=int, default=100)
     args = ap.parse_args()
