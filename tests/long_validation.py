@@ -3,6 +3,7 @@ sizes. They take minutes of host time each, so pytest does not collect them; run
 directly on a GPU machine:
 
     python -u tests/long_validation.py particle   # 256^3 particle, first 2000 steps, FP64 + mixed
+    python -u tests/long_validation.py particle_inputs   # mixed against the oracle on FP32 fields
     python -u tests/long_validation.py serve      # the sampled served job, its full length
     python -u tests/long_validation.py batch      # 8 of the 512 batched particles, 20 000 steps
     python -u tests/long_validation.py film       # 2048 x 256 x 256 film, first 200 steps
@@ -95,6 +96,20 @@ def case_particle(steps=2000):
         print(json.dumps(compare(f"particle 256^3 {p} {steps} steps", rec, ref, 2)), flush=True)
 
 
+def case_particle_inputs(steps=2000):
+    """The mixed path's error split in two: against the oracle on its own FP64 fields, and
+    against the oracle on the fields rounded to FP32 as the mixed path stores them (what
+    remains is the arithmetic of the mixed path)."""
+    f = synth.single_particle_large()
+    g = synth.Fields(f.F.astype(np.float32).astype(np.float64),
+                     f.delta.astype(np.float32).astype(np.float64), f.region, f.n_regions)
+    log(f"256^3 particle, {steps} steps, oracle on FP32-rounded fields")
+    rec = gpu_records(f, steps, "mixed")
+    ref, _ = oracle_segments(g, steps, 100)
+    print(json.dumps(compare(f"particle 256^3 mixed vs oracle on FP32-rounded fields, {steps} steps",
+                             rec, ref, 2)), flush=True)
+
+
 def case_serve(n_requests=100):
     trace = synth.serving_trace(n_requests, rate_hz=20.0)
     j = trace[0]                                   # the every-100th sample of the trace
@@ -150,7 +165,7 @@ def case_film(steps=200):
 
 if __name__ == "__main__":
     oracle.build(force=False)
-    cases = {"particle": case_particle, "serve": case_serve, "batch": case_batch,
-             "film": case_film}
+    cases = {"particle": case_particle, "particle_inputs": case_particle_inputs,
+             "serve": case_serve, "batch": case_batch, "film": case_film}
     for name in sys.argv[1:] or ["particle"]:
         cases[name]()
