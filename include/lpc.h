@@ -260,11 +260,21 @@ lpc_status lpc_batch_run(lpc_batch *batch, const int64_t *n_steps);
  * known traffic (bytes read + bytes written = 2 * bytes). Asynchronous. */
 lpc_status lpc_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
 
-/* Overrides the launch plan of the sweep: tile_x 64, 32 or 16 columns per tile row (0:
- * the least padding in x) and zc planes per workgroup (0: chosen from the device's
- * resident workgroups). Any plan computes the same step; the plan fixes the order of the
- * per-step sums, so results are bitwise reproducible for a given plan and agree to
- * rounding across plans. LPC_ERR_ARG if the plan's partial sums do not fit the arena. */
+/* tile_x of lpc_set_plan for linear tiles: each workgroup takes 256 consecutive sites of
+ * the x-y plane (x fastest) instead of a block of columns, so a narrow lattice leaves
+ * almost no lane idle. Available up to an nx that depends on the precision and track set
+ * (the LDS window holds 256 + 2 nx sites), and not for lattices with a mobility field or a
+ * reservoir axis. */
+#define LPC_TILE_LINEAR 1
+
+/* Overrides the launch plan of the sweep: tile_x 64, 32 or 16 columns per tile row,
+ * LPC_TILE_LINEAR, or 0 (automatic: the block width with the least padding in x within
+ * 1.5x, or linear tiles where they leave fewer lanes idle and are available), and zc planes
+ * per workgroup (0: chosen from the device's resident workgroups). Any plan computes the
+ * same step; the plan fixes the order of the per-step sums, so results are bitwise
+ * reproducible for a given plan and agree to rounding across plans. LPC_ERR_ARG if the
+ * plan's partial sums do not fit the arena, or linear tiles are asked for where they are
+ * not available. */
 lpc_status lpc_set_plan(lpc_lattice *lat, int32_t tile_x, int32_t zc);
 
 /* Launch plan of the sweep as text (tile shape, z-chunk, workgroups, steps finalised

@@ -167,7 +167,7 @@ Layout plan_layout(const lpc_config &c)
     L.K = 3 * c.n_regions + 6;
     L.storage = c.precision == LPC_PREC_FP64 ? 8 : 4;
     lpc::Geometry g{c.n[0], c.n[1], c.n[2], {c.bc[0], c.bc[1], c.bc[2]}};
-    L.plan = lpc::make_plan(g, 1, 256, 0);
+    L.plan = lpc::make_plan(g, 1, 256, 0, lpc::linear_tile_max_nx(c.precision, variant_of(c)));
     const int64_t per_step_max = int64_t(L.K) * lpc::max_sweep_blocks(g) * 8;
     L.staging = L.n < kStagingMax ? L.n : kStagingMax;
     size_t o = 0;
@@ -475,7 +475,8 @@ lpc_status lpc_create(const lpc_config *cfg, void *arena, size_t arena_bytes, vo
         const int occ = lpc::sweep_blocks_per_cu(cfg->precision, variant_of(*cfg), cfg->n_regions);
         lat->occupancy = occ;
         lat->cus = cus;
-        lat->L.plan = lpc::make_plan(g, occ, cus, 0);
+        lat->L.plan = lpc::make_plan(g, occ, cus, 0,
+                                     lpc::linear_tile_max_nx(cfg->precision, variant_of(*cfg)));
         set_chunk(lat->L);
     }
     for (int b = 0; b < 2; ++b) {
@@ -1476,7 +1477,7 @@ lpc_status lpc_batch_run(lpc_batch *batch, const int64_t *n_steps)
         std::vector<Group> groups;
         int64_t chunk = kChunkMax;
         for (uint32_t ext : {0u, lpc::kVariantExtended}) {
-            for (int32_t tx : {64, 32, 16}) {
+            for (int32_t tx : {64, 32, 16, lpc::kTileLinear}) {
                 Group gr{tx, int32_t(items.size()), 0, ext, prefix.size(), 0};
                 prefix.push_back(0);
                 for (int32_t l : active) {
@@ -1556,15 +1557,20 @@ lpc_status lpc_set_plan(lpc_lattice *lat, int32_t tile_x, int32_t zc)
 {
     if (!lat)
         return fail(LPC_ERR_ARG, "lattice is NULL");
-    if (tile_x != 0 && tile_x != 64 && tile_x != 32 && tile_x != 16)
-        return fail(LPC_ERR_ARG, "tile_x = %d is not 0, 64, 32 or 16", tile_x);
+    if (tile_x != 0 && tile_x != 64 && tile_x != 32 && tile_x != 16 && tile_x != LPC_TILE_LINEAR)
+        return fail(LPC_ERR_ARG, "tile_x = %d is not 0, 1, 64, 32 or 16", tile_x);
     if (zc < 0)
         return fail(LPC_ERR_ARG, "zc = %d is negative", zc);
+    const int32_t linear_max = lpc::linear_tile_max_nx(lat->cfg.precision, variant_of(lat->cfg));
+    if (tile_x == LPC_TILE_LINEAR && lat->cfg.n[0] > linear_max)
+        return fail(LPC_ERR_ARG,
+                    "linear tiles take nx <= %d for this precision, track set and variant "
+                    "(nx = %d)", linear_max, lat->cfg.n[0]);
     if (lpc_status s = use_device(lat))
         return s;
     lpc::Geometry g{lat->cfg.n[0], lat->cfg.n[1], lat->cfg.n[2],
                     {lat->cfg.bc[0], lat->cfg.bc[1], lat->cfg.bc[2]}};
-    lpc::SweepPlan p = lpc::make_plan(g, lat->occupancy, lat->cus, tile_x);
+    lpc::SweepPlan p = lpc::make_plan(g, lat->occupancy, lat->cus, tile_x, linear_max);
     if (zc > 0)
         p = lpc::with_z_chunk(p, g, zc);
     if (size_t(p.nblocks) * lat->L.K * 8 > lat->L.partial_bytes)

@@ -24,11 +24,16 @@ struct Geometry {
 // Launch shape of the sweep: a 1-D grid of workgroups, each owning a tx x ty x-y tile
 // and a run of zc planes. Blocks are renumbered so that each XCD gets a contiguous
 // range of tiles (hardware dispatch is round-robin over the 8 XCDs).
+// tx = kTileLinear: a tile is a run of 256 consecutive sites of the x-y plane (x fastest)
+// rather than a tx x ty block of columns; ty is then 256.
 struct SweepPlan {
     int32_t tx, ty, zc;
     int32_t gx, gy, gz;
     int64_t nblocks;
 };
+
+// SweepPlan.tx of a linear tile.
+constexpr int32_t kTileLinear = 1;
 
 // Kernel variant bit carried next to the track bits: the lattice has a mobility field or
 // a reservoir axis, and runs the extended sweep variant.
@@ -65,8 +70,15 @@ struct StepArgs {
 // Upper bound on the workgroups of any plan for g (sizes the per-step partial sums).
 int64_t max_sweep_blocks(const Geometry &g);
 // Plan for g given the resident sweep workgroups per compute unit and the compute units;
-// tile_x 64, 32 or 16 fixes the tile width, anything else picks the least x padding.
-SweepPlan make_plan(const Geometry &g, int32_t blocks_per_cu, int32_t cus, int32_t tile_x);
+// tile_x 64, 32 or 16 fixes the tile width, kTileLinear asks for linear tiles (only when
+// g.nx <= linear_nx_max), anything else picks the tiles with the fewest idle lanes.
+// linear_nx_max is the widest lattice the kernel variant runs on linear tiles (0: none).
+SweepPlan make_plan(const Geometry &g, int32_t blocks_per_cu, int32_t cus, int32_t tile_x,
+                    int32_t linear_nx_max);
+// Widest x extent the sweep variant of this precision and track set runs on linear tiles:
+// the LDS window of a linear tile holds 256 + 2 nx cells, within the share of LDS that keeps
+// two workgroups resident per compute unit. 0 for the extended variant.
+int32_t linear_tile_max_nx(int32_t precision, uint32_t track);
 // The plan with its z-chunk forced to zc planes (zc >= 1).
 SweepPlan with_z_chunk(SweepPlan p, const Geometry &g, int32_t zc);
 // Resident sweep workgroups per compute unit for this precision, track set and regions.

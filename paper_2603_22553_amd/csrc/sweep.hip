@@ -549,8 +549,26 @@ struct TileLds {
 
 // Workgroups are 256 threads: one thread per column of a TX x (256 / TX) tile of x-y
 // columns. TX is 64 for wide lattices (a wave covers one 64-site row) and 32 or 16 for
-// narrow ones, so that small boxes do not leave most lanes idle.
+// narrow ones, so that small boxes do not leave most lanes idle. A linear tile
+// (TX = kTileLinear) instead takes 256 consecutive sites of the plane in x-fastest order,
+// whatever the row length: a lattice narrower than 128 sites then keeps nearly every lane
+// busy, and each wave still reads 64 consecutive sites.
 constexpr int kThreads = 256;
+
+// LDS of one workgroup when two are resident per compute unit (160 KiB each), less room
+// for the record reduction.
+constexpr int64_t kLdsShare = 80 * 1024 - 1024;
+
+// Widest x extent run on linear tiles: their double-buffered LDS window of 256 + 2 nx cells
+// must fit the share (and one halo site per thread needs 2 nx <= 256).
+template <typename S, bool FID, bool MSD>
+constexpr int linear_nx_max()
+{
+    constexpr int64_t cell = int64_t(sizeof(TileLds<S, FID, MSD, false, 2>)) -
+                             int64_t(sizeof(TileLds<S, FID, MSD, false, 1>));
+    constexpr int64_t nx = (kLdsShare / 2 / cell - kThreads) / 2;
+    return static_cast<int>(nx > kThreads / 2 ? kThreads / 2 : nx) & ~3;
+}
 
 __device__ inline void tile_coords(const SweepPlan &p, int64_t blk, int &bx, int &by, int &bz)
 {
@@ -565,6 +583,7 @@ __device__ inline void tile_coords(const SweepPlan &p, int64_t blk, int &bx, int
 struct TileThread {
     Off own, halo;
     int li, hslot, hghost;   // hghost: reservoir face whose ghost fills the halo slot, or -1
+    int oxm, oxp, oy;        // LDS offsets of the x-1, x+1 and (+-) y neighbours from li
     bool act, has_xm, has_xp, has_ym, has_yp;
 };
 
@@ -581,7 +600,6 @@ __device__ __forceinline__ void plane_step(LDS &L, const StepArgs &a, const Tile
                                            Cell<S, FID, MSD, EXT> &nx2,
                                            Cell<S, FID, MSD, EXT> &halo, RecAcc<MAXR> &acc)
 {
-    constexpr int COLS = TX + 2;
     const Geometry &g = a.g;
     const bool zper = g.bc[2] == 0, zres = EXT && g.bc[2] == kBcReservoir;
     if (th.act)
@@ -614,19 +632,19 @@ __device__ __forceinline__ void plane_step(LDS &L, const StepArgs &a, const Tile
     Acc<S> f{};
     Cell<S, FID, MSD, EXT> nb;
     if (th.has_xm) {
-        L.get(th.li - 1, nb);
+        L.get(th.li + th.oxm, nb);
         add_link<0, -1>(cur, nb, p0, f);
     }
     if (th.has_xp) {
-        L.get(th.li + 1, nb);
+        L.get(th.li + th.oxp, nb);
         add_link<0, +1>(cur, nb, p0, f);
     }
     if (th.has_ym) {
-        L.get(th.li - COLS, nb);
+        L.get(th.li - th.oy, nb);
         add_link<1, -1>(cur, nb, p0, f);
     }
     if (th.has_yp) {
-        L.get(th.li + COLS, nb);
+        L.get(th.li + th.oy, nb);
         add_link<1, +1>(cur, nb, p0, f);
     }
     // the z ghost cells are built where they are used: filling window registers with them
@@ -658,44 +676,91 @@ __device__ __forceinline__ void plane_step(LDS &L, const StepArgs &a, const Tile
 #define LPC_MIN_WAVES 2
 #endif
 
-// One step over a TX x TY tile of x-y columns and the workgroup's run of z-planes. Each
-// thread owns one column and keeps planes z-1, z, z+1 of it in registers, with plane z+2
-// in flight; the four register sets rotate roles from plane to plane, so no move forces
-// an early wait on a prefetch. The x and y neighbours of plane z come from an LDS image of
-// the plane with a one-site halo, double-buffered so that one barrier per plane suffices.
-// The halo sites (a row below and above the tile, a column left and right of it; wrapped
-// on periodic axes, absent across closed faces) are spread over threads, one site each,
-// and fetched one plane ahead. Plane offsets are workgroup-uniform; each thread keeps only
-// the 32-bit byte offsets of its column. Beyond a reservoir face in x or y the halo slot
-// holds the face's ghost cell, set once and never reloaded; in z the ghost cell is built
-// at the first or last plane where its link is added.
-template <typename S, bool FID, bool MSD, bool EXT, int MAXR, int TX>
-__device__ __forceinline__ void sweep_tile(const StepArgs &a, const SweepPlan &p, int64_t blk)
+// Tile geometry of the sweep: TY rows of TX columns with a one-site halo, or a linear tile
+// of 256 sites with a window of one row on either side (NL cells in LDS).
+template <typename S, bool FID, bool MSD, bool EXT, int TX>
+struct TileShape {
+    static constexpr bool linear = TX == kTileLinear;
+    static constexpr int TY = linear ? kThreads : kThreads / TX;
+    static constexpr int COLS = linear ? 0 : TX + 2;
+    static constexpr int NL = linear ? kThreads + 2 * linear_nx_max<S, FID, MSD>()
+                                     : COLS * (TY + 2);
+    static_assert(linear || TX * TY >= 2 * TX + 2 * TY, "one halo site per thread");
+    static_assert(!(linear && EXT), "linear tiles run the plain variant only");
+};
+
+// Per-thread constants of a linear tile: sites s0 .. s0 + n - 1 of the plane (n <= 256).
+// LDS slot j holds plane site s0 - nx + j: the row below the run, the run, the row above
+// it. Threads t < 2 nx each fetch one halo site (slot t below, slot t + n above), wrapped
+// modulo the plane on a periodic y axis (the row below row 0 is row ny - 1), absent across
+// a closed y face. An x neighbour across a periodic x face is in the same row, nx - 1 sites
+// away; it lies inside the window too.
+__device__ inline void linear_thread(TileThread &th, const Geometry &g, int bx, int t,
+                                     uint32_t storage)
 {
-    constexpr int TY = kThreads / TX, COLS = TX + 2, NL = COLS * (TY + 2);
-    static_assert(TX * TY >= 2 * TX + 2 * TY, "one halo site per thread");
-    using C = Cell<S, FID, MSD, EXT>;
-    __shared__ TileLds<S, FID, MSD, EXT, NL> L0, L1;
-    __shared__ double red[(kThreads / kWave) * (3 * MAXR + 6)];
-    const Geometry &g = a.g;
-    int bx, by, bz;
-    tile_coords(p, blk, bx, by, bz);
-    const int t = static_cast<int>(threadIdx.x);
+    const int nx = g.nx;
+    const int64_t P = static_cast<int64_t>(g.nx) * g.ny;
+    const int64_t s0 = static_cast<int64_t>(bx) * kThreads;
+    const int n = static_cast<int>(min(static_cast<int64_t>(kThreads), P - s0));
+    const bool xper = g.bc[0] == 0, yper = g.bc[1] == 0;
+    const int64_t s = s0 + t;
+    th.act = t < n;
+    const int x = th.act ? static_cast<int>(s % nx) : 0;
+    const int y = th.act ? static_cast<int>(s / nx) : 0;
+    th.has_xm = x > 0 || xper;
+    th.has_xp = x + 1 < nx || xper;
+    th.has_ym = y > 0 || yper;
+    th.has_yp = y + 1 < g.ny || yper;
+    const uint32_t col = th.act ? static_cast<uint32_t>(s) : 0u;
+    th.own = {col * 8u, col * storage, col};
+    th.li = nx + t;
+    th.oxm = x > 0 ? -1 : nx - 1;
+    th.oxp = x + 1 < nx ? 1 : 1 - nx;
+    th.oy = nx;
+    th.hslot = -1;
+    th.hghost = -1;
+    uint32_t hcol = 0u;
+    if (t < 2 * nx) {
+        const int j = t < nx ? t : t + n;
+        int64_t q = s0 - nx + j;
+        if (q < 0)
+            q = yper ? q + P : -1;
+        else if (q >= P)
+            q = yper ? q - P : -1;
+        if (q >= 0) {
+            th.hslot = j;
+            hcol = static_cast<uint32_t>(q);
+        }
+    }
+    th.halo = {hcol * 8u, hcol * storage, hcol};
+}
+
+// Per-thread constants of a TX x TY block of columns: the thread's column, its neighbours'
+// existence and its halo site (a row below and above the block, a column left and right of
+// it; wrapped on periodic axes, absent across closed faces, a ghost cell across reservoir
+// faces).
+template <bool EXT, int TX>
+__device__ inline void block_thread(TileThread &th, const Geometry &g, int bx, int by, int t,
+                                    uint32_t storage)
+{
+    constexpr int TY = kThreads / TX, COLS = TX + 2;
     const int tx = t % TX, ty = t / TX;
     const int x0 = bx * TX, y0 = by * TY;
     const int x = x0 + tx, y = y0 + ty;
     const int cols = min(TX, g.nx - x0), rows = min(TY, g.ny - y0);
-    const bool xper = g.bc[0] == 0, yper = g.bc[1] == 0, zper = g.bc[2] == 0;
+    const bool xper = g.bc[0] == 0, yper = g.bc[1] == 0;
     const bool xres = EXT && g.bc[0] == kBcReservoir, yres = EXT && g.bc[1] == kBcReservoir;
-    TileThread th;
     th.act = tx < cols && ty < rows;
     th.has_xm = x > 0 || xper || xres;
     th.has_xp = x + 1 < g.nx || xper || xres;
     th.has_ym = y > 0 || yper || yres;
     th.has_yp = y + 1 < g.ny || yper || yres;
     const uint32_t col = th.act ? static_cast<uint32_t>(x + g.nx * y) : 0u;
-    th.own = {col * 8u, col * static_cast<uint32_t>(sizeof(S)), col};
+    th.own = {col * 8u, col * storage, col};
     th.li = (ty + 1) * COLS + tx + 1;
+    th.oxm = -1;
+    th.oxp = 1;
+    th.oy = COLS;
     th.hslot = -1;
     {
         int hx = -1, hy = -1, face = -1;
@@ -736,8 +801,38 @@ __device__ __forceinline__ void sweep_tile(const StepArgs &a, const SweepPlan &p
         th.hghost = th.hslot >= 0 ? face : -1;
         const uint32_t hcol = th.hslot >= 0 && face < 0 ? static_cast<uint32_t>(hx + g.nx * hy)
                                                         : 0u;
-        th.halo = {hcol * 8u, hcol * static_cast<uint32_t>(sizeof(S)), hcol};
+        th.halo = {hcol * 8u, hcol * storage, hcol};
     }
+}
+
+// One step over a tile of x-y columns (a TX x TY block, or a linear run of 256 sites) and
+// the workgroup's run of z-planes. Each thread owns one column and keeps planes z-1, z, z+1
+// of it in registers, with plane z+2 in flight; the four register sets rotate roles from
+// plane to plane, so no move forces an early wait on a prefetch. The x and y neighbours of
+// plane z come from an LDS image of the plane with its halo, double-buffered so that one
+// barrier per plane suffices. The halo sites are spread over threads, one site each, and
+// fetched one plane ahead. Plane offsets are workgroup-uniform; each thread keeps only the
+// 32-bit byte offsets of its column. Beyond a reservoir face in x or y the halo slot holds
+// the face's ghost cell, set once and never reloaded; in z the ghost cell is built at the
+// first or last plane where its link is added.
+template <typename S, bool FID, bool MSD, bool EXT, int MAXR, int TX>
+__device__ __forceinline__ void sweep_tile(const StepArgs &a, const SweepPlan &p, int64_t blk)
+{
+    using Shape = TileShape<S, FID, MSD, EXT, TX>;
+    constexpr int NL = Shape::NL;
+    using C = Cell<S, FID, MSD, EXT>;
+    __shared__ TileLds<S, FID, MSD, EXT, NL> L0, L1;
+    __shared__ double red[(kThreads / kWave) * (3 * MAXR + 6)];
+    const Geometry &g = a.g;
+    int bx, by, bz;
+    tile_coords(p, blk, bx, by, bz);
+    const int t = static_cast<int>(threadIdx.x);
+    TileThread th;
+    if constexpr (Shape::linear)
+        linear_thread(th, g, bx, t, static_cast<uint32_t>(sizeof(S)));
+    else
+        block_thread<EXT, TX>(th, g, bx, by, t, static_cast<uint32_t>(sizeof(S)));
+    const bool zper = g.bc[2] == 0;
     const S *F = static_cast<const S *>(a.F);
     const S *MU = static_cast<const S *>(a.mu);
     const S *TH = static_cast<const S *>(a.theta);
@@ -848,14 +943,20 @@ __global__ __launch_bounds__(kThreads) void k_record_tile(StepArgs a, SweepPlan 
         return;
     int bx, by, bz;
     tile_coords(p, blk, bx, by, bz);
-    const int x = bx * p.tx + static_cast<int>(threadIdx.x) % p.tx;
-    const int y = by * p.ty + static_cast<int>(threadIdx.x) / p.tx;
+    const int64_t plane = static_cast<int64_t>(a.g.nx) * a.g.ny;
+    int64_t col = -1;
+    if (p.tx == kTileLinear) {
+        const int64_t s = static_cast<int64_t>(bx) * kThreads + threadIdx.x;
+        col = s < plane ? s : -1;
+    } else {
+        const int x = bx * p.tx + static_cast<int>(threadIdx.x) % p.tx;
+        const int y = by * p.ty + static_cast<int>(threadIdx.x) / p.tx;
+        col = x < a.g.nx && y < a.g.ny ? x + static_cast<int64_t>(a.g.nx) * y : -1;
+    }
     const View<S> src = typed<S>(a.src);
     RecAcc<MAXR> acc;
     acc.zero();
-    if (x < a.g.nx && y < a.g.ny) {
-        const int64_t plane = static_cast<int64_t>(a.g.nx) * a.g.ny;
-        const int64_t col = x + static_cast<int64_t>(a.g.nx) * y;
+    if (col >= 0) {
         const int z1 = min(a.g.nz, (bz + 1) * p.zc);
         for (int z = bz * p.zc; z < z1; ++z)
             record_site<S, FID, MSD, MAXR>(a, src, col + plane * z, acc);
@@ -1023,7 +1124,14 @@ struct ListLauncher {
     {
         const int64_t padded = (L->total + 7) / 8 * 8;
         const dim3 grid(static_cast<unsigned>(padded)), block(kThreads);
-        if (L->tile_x == 64)
+        if (L->tile_x == kTileLinear) {
+            if constexpr (EXT)
+                return hipErrorInvalidValue;        // plans never give the extended variant these
+            else
+                hipLaunchKernelGGL((k_sweep_tile<S, FID, MSD, false, MAXR, kTileLinear>), grid, block,
+                                   0, s, L->items, L->prefix, L->n_items, L->total, padded,
+                                   L->parity, L->slot);
+        } else if (L->tile_x == 64)
             hipLaunchKernelGGL((k_sweep_tile<S, FID, MSD, EXT, MAXR, 64>), grid, block, 0, s, L->items,
                                L->prefix, L->n_items, L->total, padded, L->parity, L->slot);
         else if (L->tile_x == 32)
@@ -1098,25 +1206,48 @@ int32_t tile_width(int32_t nx)
     return 16;
 }
 
+// Tiles of one plane for tile width tx (kTileLinear: linear tiles).
+int64_t plane_tiles(const Geometry &g, int32_t tx)
+{
+    if (tx == kTileLinear)
+        return (int64_t(g.nx) * g.ny + kThreads - 1) / kThreads;
+    const int32_t ty = kThreads / tx;
+    return int64_t((g.nx + tx - 1) / tx) * ((g.ny + ty - 1) / ty);
+}
+
 int64_t max_sweep_blocks(const Geometry &g)
 {
     int64_t most = 0;
-    for (int32_t tx : {64, 32, 16}) {
-        const int32_t ty = kThreads / tx;
-        const int64_t tiles = int64_t((g.nx + tx - 1) / tx) * ((g.ny + ty - 1) / ty);
+    for (int32_t tx : {64, 32, 16, kTileLinear}) {
+        const int64_t tiles = plane_tiles(g, tx);
         const int64_t gz = std::max<int64_t>((g.nz + 7) / 8, (8192 + tiles - 1) / tiles);
         most = std::max(most, tiles * std::min<int64_t>(g.nz, gz));
     }
     return most;
 }
 
-SweepPlan make_plan(const Geometry &g, int32_t blocks_per_cu, int32_t cus, int32_t tile_x)
+SweepPlan make_plan(const Geometry &g, int32_t blocks_per_cu, int32_t cus, int32_t tile_x,
+                    int32_t linear_nx_max)
 {
     SweepPlan p{};
-    p.tx = tile_x == 64 || tile_x == 32 || tile_x == 16 ? tile_x : tile_width(g.nx);
-    p.ty = kThreads / p.tx;
-    p.gx = (g.nx + p.tx - 1) / p.tx;
-    p.gy = (g.ny + p.ty - 1) / p.ty;
+    const bool linear_ok = g.nx <= linear_nx_max;
+    if (tile_x == 64 || tile_x == 32 || tile_x == 16 || (tile_x == kTileLinear && linear_ok)) {
+        p.tx = tile_x;
+    } else {
+        // block tiles by the padding rule, unless linear tiles leave fewer lanes idle
+        p.tx = tile_width(g.nx);
+        if (linear_ok && plane_tiles(g, kTileLinear) < plane_tiles(g, p.tx))
+            p.tx = kTileLinear;
+    }
+    if (p.tx == kTileLinear) {
+        p.ty = kThreads;
+        p.gx = static_cast<int32_t>(plane_tiles(g, kTileLinear));
+        p.gy = 1;
+    } else {
+        p.ty = kThreads / p.tx;
+        p.gx = (g.nx + p.tx - 1) / p.tx;
+        p.gy = (g.ny + p.ty - 1) / p.ty;
+    }
     const int64_t tiles = static_cast<int64_t>(p.gx) * p.gy;
     const int64_t conc = std::max(1, blocks_per_cu) * static_cast<int64_t>(std::max(1, cus));
     const int64_t gz_cap = std::max<int64_t>((g.nz + 7) / 8, (8192 + tiles - 1) / tiles);
@@ -1169,6 +1300,27 @@ struct OccupancyQuery {
             kThreads, 0);
     }
 };
+
+struct LinearLimit {
+    template <typename S, bool FID, bool MSD, bool EXT, int>
+    static hipError_t go(const SweepPlan &, const StepArgs &, hipStream_t, int *out)
+    {
+        *out = EXT ? 0 : linear_nx_max<S, FID, MSD>();
+        return hipSuccess;
+    }
+};
+
+int32_t linear_tile_max_nx(int32_t precision, uint32_t track)
+{
+    StepArgs a{};
+    a.precision = precision;
+    a.track = track;
+    a.R = 1;
+    int n = 0;
+    if (by_precision<LinearLimit>(SweepPlan{}, a, nullptr, &n) != hipSuccess)
+        return 0;
+    return n;
+}
 
 int sweep_blocks_per_cu(int32_t precision, uint32_t track, int32_t R)
 {
