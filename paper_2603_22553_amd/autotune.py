@@ -1,8 +1,9 @@
 """Launch-plan autotuner for the lattice sweep.
 
 For a lattice shape (with its boundaries, precision, track set and region count) it times
-the sweep under each candidate plan, tile width 64 / 32 / 16 combined with the automatic
-z-chunk, half of it and twice it, on a scratch lattice, and keeps the fastest. Results are
+the sweep under each candidate plan, tile width 64 / 32 / 16 or linear tiles (where the
+variant takes them) combined with the automatic z-chunk, half of it and twice it, on a
+scratch lattice, and keeps the fastest. Results are
 cached in a JSON file keyed by device name, ROCm version and configuration, so a shape is
 timed once per machine. Any plan computes the same step (only the order of the per-step
 sums changes), so tuning never changes what is computed.
@@ -47,13 +48,31 @@ def _save_cache(path, data):
         pass
 
 
-def candidates(shape_xyz, auto_zc: int):
+LINEAR = 1      # tile_x of linear tiles (256 consecutive sites of the x-y plane)
+
+
+def candidates(shape_xyz, auto_zc: int, linear: bool = True):
+    """Candidate (tile_x, zc) plans: block widths within 1.5x of the least x padding, and
+    linear tiles when `linear` (the lattice's variant takes them at this nx)."""
     nx, _, nz = shape_xyz
     pads = {tx: -(-nx // tx) * tx for tx in (64, 32, 16)}
     best_pad = min(pads.values())
     widths = [tx for tx in (64, 32, 16) if pads[tx] <= 1.5 * best_pad]
+    if linear:
+        widths.append(LINEAR)
     zcs = sorted({max(1, min(nz, z)) for z in (auto_zc, auto_zc // 2, 2 * auto_zc)})
     return [(tx, zc) for tx in widths for zc in zcs]
+
+
+def _takes_linear(lat) -> bool:
+    """Whether the lattice's sweep variant runs linear tiles at its width (the library
+    refuses the plan otherwise); leaves the lattice on its automatic plan."""
+    try:
+        lat.set_plan(LINEAR, 0)
+    except L.LpcError:
+        return False
+    lat.set_plan(0, 0)
+    return True
 
 
 def tune(shape_xyz, bc=("periodic",) * 3, precision="fp64", track=("fid", "msd"), n_regions=1,
@@ -68,8 +87,9 @@ def tune(shape_xyz, bc=("periodic",) * 3, precision="fp64", track=("fid", "msd")
     rng = np.random.default_rng(0)
     probe = L.Lattice(shape_xyz, bc, precision, track, n_regions, max_records=2)
     auto_zc = probe.plan["zc"]
+    linear = _takes_linear(probe)
     probe.close()
-    cands = candidates(shape_xyz, auto_zc)
+    cands = candidates(shape_xyz, auto_zc, linear)
     lat = L.Lattice(shape_xyz, bc, precision, track, n_regions,
                     max_records=len(cands) * (steps + warmup) + 1)
     lat.set_free_energy(rng.normal(0.0, 1.0, size=(nz, ny, nx)))

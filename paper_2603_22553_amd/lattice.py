@@ -117,7 +117,9 @@ class Lattice:
         self.close()
 
     def set_plan(self, tile_x: int = 0, zc: int = 0):
-        """Launch plan override: tile width 64/32/16 (0 automatic), z-chunk (0 automatic)."""
+        """Launch plan override: tile width 64/32/16, 1 for linear tiles (256 consecutive
+        sites of the x-y plane; narrow lattices of the plain variant only) or 0 automatic;
+        z-chunk (0 automatic)."""
         N.call("lpc_set_plan", self.handle, int(tile_x), int(zc))
 
     @property
