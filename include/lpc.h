@@ -260,6 +260,18 @@ lpc_status lpc_batch_run(lpc_batch *batch, const int64_t *n_steps);
  * known traffic (bytes read + bytes written = 2 * bytes). Asynchronous. */
 lpc_status lpc_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
 
+/* Calibration utility: the memory pattern of the FP64 sweep with FID and moments, without
+ * its arithmetic. in[0..11] and out[0..8] are device arrays of nx * ny * nz doubles (x
+ * fastest); outputs must not overlap any array. Workgroups take 64 x 4 blocks of columns
+ * and runs of zc planes; each thread reads the 12 values of its column one plane ahead and
+ * writes 9 past the caches, with one barrier per plane, as the sweep does (minus its halo
+ * and its arithmetic). out[k] = in[k] + in[9] + in[10] * in[11]. Bytes moved are
+ * 21 * 8 * nx * ny * nz: the bandwidth this pattern allows, against which the sweep's
+ * counter traffic can be set. LPC_ERR_ARG on NULL arrays, overlapping outputs, sizes or zc
+ * below 1, or a grid beyond 2^31 - 1 workgroups. Asynchronous on `stream`. */
+lpc_status lpc_stream_columns(const double *const *in, double *const *out, int32_t nx,
+                              int32_t ny, int32_t nz, int32_t zc, void *stream);
+
 /* tile_x of lpc_set_plan for linear tiles: each workgroup takes 256 consecutive sites of
  * the x-y plane (x fastest) instead of a block of columns, so a narrow lattice leaves
  * almost no lane idle. Available up to an nx that depends on the precision and track set

@@ -1553,6 +1553,46 @@ lpc_status lpc_stream_copy(const void *src, void *dst, size_t bytes, void *strea
     return ok();
 }
 
+lpc_status lpc_stream_columns(const double *const *in, double *const *out, int32_t nx,
+                              int32_t ny, int32_t nz, int32_t zc, void *stream)
+{
+    if (!in || !out)
+        return fail(LPC_ERR_ARG, "NULL array list");
+    if (nx < 1 || ny < 1 || nz < 1 || zc < 1)
+        return fail(LPC_ERR_ARG, "sizes and zc must be >= 1");
+    const int64_t n = int64_t(nx) * ny * nz;
+    const int64_t blocks = int64_t((nx + 63) / 64) * ((ny + 3) / 4) * ((nz + zc - 1) / zc);
+    if (blocks > INT32_MAX)
+        return fail(LPC_ERR_ARG, "too many workgroups; raise zc");
+    const size_t bytes = size_t(n) * 8;
+    lpc::ColumnArrays c{};
+    for (int k = 0; k < lpc::kColumnIn; ++k) {
+        if (!in[k])
+            return fail(LPC_ERR_ARG, "input array %d is NULL", k);
+        c.in[k] = in[k];
+    }
+    for (int k = 0; k < lpc::kColumnOut; ++k) {
+        if (!out[k])
+            return fail(LPC_ERR_ARG, "output array %d is NULL", k);
+        c.out[k] = out[k];
+    }
+    // outputs overlap nothing (inputs may repeat: they are only read)
+    auto overlap = [bytes](const void *p, const void *q) {
+        const char *a = static_cast<const char *>(p), *b = static_cast<const char *>(q);
+        return a < b + bytes && b < a + bytes;
+    };
+    for (int k = 0; k < lpc::kColumnOut; ++k) {
+        for (int j = 0; j < lpc::kColumnIn; ++j)
+            if (overlap(out[k], in[j]))
+                return fail(LPC_ERR_ARG, "output %d overlaps input %d", k, j);
+        for (int j = 0; j < k; ++j)
+            if (overlap(out[k], out[j]))
+                return fail(LPC_ERR_ARG, "outputs %d and %d overlap", j, k);
+    }
+    LPC_HIP(lpc::launch_stream_columns(c, nx, ny, nz, zc, static_cast<hipStream_t>(stream)));
+    return ok();
+}
+
 lpc_status lpc_set_plan(lpc_lattice *lat, int32_t tile_x, int32_t zc)
 {
     if (!lat)

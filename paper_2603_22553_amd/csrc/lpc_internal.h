@@ -166,4 +166,14 @@ hipError_t launch_profile(const double *rho, const Geometry &g, int32_t axis, do
 // Plain copy of n16 16-byte words (calibration kernel).
 hipError_t launch_stream_copy(const void *src, void *dst, int64_t n16, hipStream_t s);
 
+// The FP64 full sweep's column streams without its arithmetic (calibration kernel): 12
+// arrays read and 9 written, nx * ny * nz doubles each.
+constexpr int kColumnIn = 12, kColumnOut = 9;
+struct ColumnArrays {
+    const double *in[kColumnIn];
+    double *out[kColumnOut];
+};
+hipError_t launch_stream_columns(const ColumnArrays &c, int32_t nx, int32_t ny, int32_t nz,
+                                 int32_t zc, hipStream_t s);
+
 }  // namespace lpc

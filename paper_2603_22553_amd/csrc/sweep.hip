@@ -1097,6 +1097,48 @@ __global__ __launch_bounds__(256) void k_stream_copy(const f32x4 *__restrict__ s
             __builtin_nontemporal_store(v[k], dst + base + k * 256);
 }
 
+// The FP64 full sweep's memory pattern without its arithmetic: workgroups of 64 x 4 columns
+// marching a run of z-planes, each thread reading the 12 values of its column one plane
+// ahead and writing 9 past the caches, one barrier per plane. Each output is its input plus
+// a value formed from the other three inputs, so no load can be dropped.
+__global__ __launch_bounds__(kThreads, 2) void k_stream_columns(ColumnArrays c, int nx, int ny,
+                                                                int nz, int zc, int tiles_x,
+                                                                int tiles_y)
+{
+    constexpr int TX = 64, TY = kThreads / TX;
+    const int t = static_cast<int>(threadIdx.x);
+    const int tiles = tiles_x * tiles_y;
+    const int tile = static_cast<int>(blockIdx.x % tiles);
+    const int chunk = static_cast<int>(blockIdx.x / tiles);
+    const int x = (tile % tiles_x) * TX + t % TX, y = (tile / tiles_x) * TY + t / TX;
+    const int z0 = chunk * zc, z1 = min(nz, z0 + zc);
+    const bool act = x < nx && y < ny;
+    const int64_t plane = static_cast<int64_t>(nx) * ny, col = x + static_cast<int64_t>(nx) * y;
+    double v[2][kColumnIn];
+    auto load = [&](double *d, int z) {
+#pragma unroll
+        for (int k = 0; k < kColumnIn; ++k)
+            d[k] = act && z < z1 ? c.in[k][plane * z + col] : 0.0;
+    };
+    auto store = [&](const double *d, int z) {
+        if (!(act && z < z1))
+            return;
+        const double e = d[kColumnOut] + d[kColumnOut + 1] * d[kColumnOut + 2];
+#pragma unroll
+        for (int k = 0; k < kColumnOut; ++k)
+            __builtin_nontemporal_store(d[k] + e, c.out[k] + plane * z + col);
+    };
+    load(v[0], z0);
+    for (int z = z0; z < z1; z += 2) {
+        load(v[1], z + 1);
+        __syncthreads();
+        store(v[0], z);
+        load(v[0], z + 2);
+        __syncthreads();
+        store(v[1], z + 1);
+    }
+}
+
 int grid_for(int64_t n, int threads)
 {
     int64_t g = (n + threads - 1) / threads;
@@ -1431,6 +1473,16 @@ hipError_t launch_stream_copy(const void *src, void *dst, int64_t n16, hipStream
         return hipSuccess;
     hipLaunchKernelGGL(k_stream_copy, dim3(static_cast<unsigned>((n16 + 1023) / 1024)), dim3(256),
                        0, s, static_cast<const f32x4 *>(src), static_cast<f32x4 *>(dst), n16);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_columns(const ColumnArrays &c, int32_t nx, int32_t ny, int32_t nz,
+                                 int32_t zc, hipStream_t s)
+{
+    const int tiles_x = (nx + 63) / 64, tiles_y = (ny + 3) / 4;
+    const int64_t blocks = int64_t(tiles_x) * tiles_y * ((nz + zc - 1) / zc);
+    hipLaunchKernelGGL(k_stream_columns, dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0, s,
+                       c, nx, ny, nz, zc, tiles_x, tiles_y);
     return hipGetLastError();
 }
 

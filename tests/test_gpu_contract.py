@@ -204,3 +204,29 @@ def test_plan_override_and_autotune(tmp_path):
     tx, zc = autotune.tune((70, 20, 33), n_regions=2, steps=5, cache_path=cache)
     assert (tx, zc) in autotune.candidates((70, 20, 33), zc) or tx in (64, 32, 16)
     assert autotune.tune((70, 20, 33), n_regions=2, steps=5, cache_path=cache) == (tx, zc)
+
+
+def test_stream_columns_calibration():
+    """lpc_stream_columns computes out[k] = in[k] + in[9] + in[10] * in[11] on a ragged
+    lattice (tiles and z-chunks cut short), and rejects overlapping outputs."""
+    import ctypes
+    shape = (70, 9, 13)
+    n = shape[0] * shape[1] * shape[2]
+    buf = torch.rand(21 * n, dtype=torch.float64, device="cuda")
+    arr = [buf[k * n:(k + 1) * n] for k in range(21)]
+    ins = (ctypes.c_void_p * 12)(*[t.data_ptr() for t in arr[:12]])
+    outs = (ctypes.c_void_p * 9)(*[t.data_ptr() for t in arr[12:]])
+    s = torch.cuda.current_stream()
+    N.call("lpc_stream_columns", ins, outs, *shape, 5, ctypes.c_void_p(s.cuda_stream))
+    s.synchronize()
+    host = buf.cpu().numpy().reshape(21, n)
+    e = host[9] + host[10] * host[11]     # the kernel may fuse the product into an FMA
+    for k in range(9):
+        assert np.allclose(host[12 + k], host[k] + e, rtol=1e-15, atol=0.0)
+    bad = (ctypes.c_void_p * 9)(*[arr[12].data_ptr()] * 9)
+    with pytest.raises(N.LpcError) as err:
+        N.call("lpc_stream_columns", ins, bad, *shape, 5, ctypes.c_void_p(s.cuda_stream))
+    assert err.value.status == N.LPC_ERR_ARG
+    with pytest.raises(N.LpcError) as err:
+        N.call("lpc_stream_columns", ins, outs, *shape, 0, ctypes.c_void_p(s.cuda_stream))
+    assert err.value.status == N.LPC_ERR_ARG
