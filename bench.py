@@ -203,7 +203,7 @@ def workload_batch(args):
         lats = []
         for f in fields:
             lat = Lattice(f.shape_xyz, precision=prec, n_regions=f.n_regions,
-                          max_records=steps + args.warmup + 1)
+                          max_records=steps + args.warmup + 1, batched=True)
             lat.set_fields(f)
             lat.init_state("uniform")
             lats.append(lat)
@@ -458,7 +458,7 @@ def workload_serve(args):
     for j in jobs[:n_alone]:
         nz, ny, nx = j.fields.F.shape
         with Lattice((nx, ny, nz), precision="mixed", track=("fid",), n_regions=2,
-                     max_records=j.n_steps + 1) as lat:
+                     max_records=j.n_steps + 1, batched=True) as lat:
             lat.set_fields(j.fields)
             lat.init_state("uniform")
             lat.run(j.n_steps)

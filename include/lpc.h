@@ -66,8 +66,13 @@ enum { LPC_BC_PERIODIC = 0, LPC_BC_CLOSED = 1, LPC_BC_RESERVOIR = 2 };
 
 /* Options. MOBILITY adds a per-site mobility field mu (lpc_set_mobility): both hop
  * probabilities of the link i-j are scaled by alpha_ij = min(mu_i, mu_j), one factor for
- * both directions as detailed balance requires (section 2.2, after Eq. (7)). */
-enum { LPC_OPT_MOBILITY = 1u };
+ * both directions as detailed balance requires (section 2.2, after Eq. (7)). BATCHED
+ * plans the lattice for stepping in a batch (lpc_batch_run) with others: its automatic
+ * plan takes z-chunks of at least 16 planes (fewer, longer workgroups with less re-read
+ * at chunk ends), since the batch rather than the lattice alone fills the device. It
+ * changes no result beyond the order of the per-step sums; solo runs of the lattice use
+ * the same plan and give the same bits as its batched runs. */
+enum { LPC_OPT_MOBILITY = 1u, LPC_OPT_BATCHED = 2u };
 
 /* FP64: every field, state array and operation in double. MIXED: populations stored
  * and updated in double; free energy, phase, magnetisation and moments stored and

@@ -18,6 +18,7 @@ STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_OOM", 3: "ERR_DEVICE", 4: "ERR_ST
                 5: "ERR_NONFINITE", 6: "ERR_CONSERVATION"}
 BC_PERIODIC, BC_CLOSED, BC_RESERVOIR = 0, 1, 2
 OPT_MOBILITY = 1
+OPT_BATCHED = 2
 PREC_FP64, PREC_MIXED = 0, 1
 TRACK_FID, TRACK_MSD = 1, 2
 INIT_UNIFORM, INIT_BOLTZMANN, INIT_USER = 0, 1, 2

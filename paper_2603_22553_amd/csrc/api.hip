@@ -109,6 +109,12 @@ bool reservoir_of(const lpc_config &c)
            c.bc[2] == LPC_BC_RESERVOIR;
 }
 // Track bits plus the kernel variant bits of the configuration.
+// Least z-chunk of automatic plans: 4 planes alone, 16 for lattices stepped in batches.
+int32_t zc_floor(const lpc_config &c)
+{
+    return (c.options & LPC_OPT_BATCHED) ? 16 : 4;
+}
+
 uint32_t variant_of(const lpc_config &c)
 {
     return c.track | (mobility_of(c) || reservoir_of(c) ? lpc::kVariantExtended : 0u);
@@ -134,7 +140,7 @@ lpc_status validate_config(const lpc_config *c)
         return fail(LPC_ERR_ARG, "track bits 0x%x unknown", c->track);
     if (c->n_regions < 1 || c->n_regions > LPC_MAX_REGIONS)
         return fail(LPC_ERR_ARG, "n_regions = %d outside 1..%d", c->n_regions, LPC_MAX_REGIONS);
-    if (c->options & ~uint32_t(LPC_OPT_MOBILITY))
+    if (c->options & ~uint32_t(LPC_OPT_MOBILITY | LPC_OPT_BATCHED))
         return fail(LPC_ERR_ARG, "option bits 0x%x unknown", c->options);
     if (!std::isfinite(c->p_hop) || c->p_hop < 0.0 || 6.0 * c->p_hop > 1.0)
         return fail(LPC_ERR_ARG, "p_hop = %g must satisfy 0 <= 6 p_hop <= 1", c->p_hop);
@@ -167,7 +173,8 @@ Layout plan_layout(const lpc_config &c)
     L.K = 3 * c.n_regions + 6;
     L.storage = c.precision == LPC_PREC_FP64 ? 8 : 4;
     lpc::Geometry g{c.n[0], c.n[1], c.n[2], {c.bc[0], c.bc[1], c.bc[2]}};
-    L.plan = lpc::make_plan(g, 1, 256, 0, lpc::linear_tile_max_nx(c.precision, variant_of(c)));
+    L.plan = lpc::make_plan(g, 1, 256, 0, lpc::linear_tile_max_nx(c.precision, variant_of(c)),
+                            zc_floor(c));
     const int64_t per_step_max = int64_t(L.K) * lpc::max_sweep_blocks(g) * 8;
     L.staging = L.n < kStagingMax ? L.n : kStagingMax;
     size_t o = 0;
@@ -476,7 +483,8 @@ lpc_status lpc_create(const lpc_config *cfg, void *arena, size_t arena_bytes, vo
         lat->occupancy = occ;
         lat->cus = cus;
         lat->L.plan = lpc::make_plan(g, occ, cus, 0,
-                                     lpc::linear_tile_max_nx(cfg->precision, variant_of(*cfg)));
+                                     lpc::linear_tile_max_nx(cfg->precision, variant_of(*cfg)),
+                                     zc_floor(*cfg));
         set_chunk(lat->L);
     }
     for (int b = 0; b < 2; ++b) {
@@ -1610,7 +1618,8 @@ lpc_status lpc_set_plan(lpc_lattice *lat, int32_t tile_x, int32_t zc)
         return s;
     lpc::Geometry g{lat->cfg.n[0], lat->cfg.n[1], lat->cfg.n[2],
                     {lat->cfg.bc[0], lat->cfg.bc[1], lat->cfg.bc[2]}};
-    lpc::SweepPlan p = lpc::make_plan(g, lat->occupancy, lat->cus, tile_x, linear_max);
+    lpc::SweepPlan p = lpc::make_plan(g, lat->occupancy, lat->cus, tile_x, linear_max,
+                                      zc_floor(lat->cfg));
     if (zc > 0)
         p = lpc::with_z_chunk(p, g, zc);
     if (size_t(p.nblocks) * lat->L.K * 8 > lat->L.partial_bytes)

@@ -72,9 +72,10 @@ int64_t max_sweep_blocks(const Geometry &g);
 // Plan for g given the resident sweep workgroups per compute unit and the compute units;
 // tile_x 64, 32 or 16 fixes the tile width, kTileLinear asks for linear tiles (only when
 // g.nx <= linear_nx_max), anything else picks the tiles with the fewest idle lanes.
-// linear_nx_max is the widest lattice the kernel variant runs on linear tiles (0: none).
+// linear_nx_max is the widest lattice the kernel variant runs on linear tiles (0: none);
+// automatic z-chunks are at least zc_floor planes (or the whole axis).
 SweepPlan make_plan(const Geometry &g, int32_t blocks_per_cu, int32_t cus, int32_t tile_x,
-                    int32_t linear_nx_max);
+                    int32_t linear_nx_max, int32_t zc_floor);
 // Widest x extent the sweep variant of this precision and track set runs on linear tiles:
 // the LDS window of a linear tile holds 256 + 2 nx cells, within the share of LDS that keeps
 // two workgroups resident per compute unit. 0 for the extended variant.

@@ -34,7 +34,8 @@ def p_hop_from_residence_time(tau_s: float, dt_s: float) -> float:
 
 def make_config(shape_xyz, bc=("periodic",) * 3, precision="fp64", track=("fid", "msd"),
                 n_regions=1, p_hop=1.0 / 7.0, dt_s=5e-6, larmor_hz=400e6, spacing_m=0.5e-9,
-                max_records=1, conservation_tol=1e-12, mobility=False) -> N.Config:
+                max_records=1, conservation_tol=1e-12, mobility=False,
+                batched=False) -> N.Config:
     cfg = N.Config()
     for a in range(3):
         cfg.n[a] = int(shape_xyz[a])
@@ -46,7 +47,7 @@ def make_config(shape_xyz, bc=("periodic",) * 3, precision="fp64", track=("fid",
         t |= {"fid": N.TRACK_FID, "msd": N.TRACK_MSD}[name]
     cfg.track = t
     cfg.n_regions = int(n_regions)
-    cfg.options = N.OPT_MOBILITY if mobility else 0
+    cfg.options = (N.OPT_MOBILITY if mobility else 0) | (N.OPT_BATCHED if batched else 0)
     cfg.p_hop = float(p_hop)
     cfg.dt_s = float(dt_s)
     cfg.larmor_hz = float(larmor_hz)
@@ -66,14 +67,17 @@ class Lattice:
     """A lattice of nx*ny*nz sites resident in one device arena.
 
     shape_xyz: (nx, ny, nz); host arrays use shape (nz, ny, nx) (x fastest).
+    mobility: adds the per-site mobility field. batched: plans the lattice for stepping in
+    a Batch with others (longer z-chunks); solo runs then use the same plan and bits.
     """
 
     def __init__(self, shape_xyz, bc=("periodic",) * 3, precision="fp64", track=("fid", "msd"),
                  n_regions=1, p_hop=1.0 / 7.0, dt_s=5e-6, larmor_hz=400e6, spacing_m=0.5e-9,
                  max_records=1, conservation_tol=1e-12, device=None, stream=None,
-                 mobility=False):
+                 mobility=False, batched=False):
         self.cfg = make_config(shape_xyz, bc, precision, track, n_regions, p_hop, dt_s,
-                               larmor_hz, spacing_m, max_records, conservation_tol, mobility)
+                               larmor_hz, spacing_m, max_records, conservation_tol, mobility,
+                               batched)
         self.shape_xyz = tuple(int(v) for v in shape_xyz)
         self.n_sites = int(np.prod(self.shape_xyz))
         self.n_regions = int(n_regions)

@@ -61,7 +61,8 @@ class GpuExecutor:
     def _cfg(self, job: Job):
         nz, ny, nx = job.fields.F.shape
         return self._lat.make_config((nx, ny, nz), job.bc, self.precision, self.track,
-                                     job.fields.n_regions, max_records=job.n_steps + 1)
+                                     job.fields.n_regions, max_records=job.n_steps + 1,
+                                     batched=True)
 
     def footprint(self, job: Job) -> int:
         return self._lat.footprint(self._cfg(job)) + self._lat.batch_footprint(1)
@@ -70,7 +71,7 @@ class GpuExecutor:
         nz, ny, nx = job.fields.F.shape
         lat = self._lat.Lattice((nx, ny, nz), job.bc, self.precision, self.track,
                                 job.fields.n_regions, max_records=job.n_steps + 1,
-                                device=self.device)
+                                device=self.device, batched=True)
         lat.set_fields(job.fields)
         lat.init_state("uniform")
         return lat

@@ -139,7 +139,8 @@ def run_batch(systems, steps: int = 50000, tau_s: float = 1e-3, dt_s: float = 5e
             f = sysm.fields
             lat = Lattice(f.shape_xyz, bc=("periodic", "periodic", "closed"),
                           precision=precision, n_regions=3, p_hop=p_hop, dt_s=dt_s,
-                          larmor_hz=larmor_hz, spacing_m=spacing_m, max_records=steps + 1)
+                          larmor_hz=larmor_hz, spacing_m=spacing_m, max_records=steps + 1,
+                          batched=True)
             lats.append(lat)
             lat.set_fields(f)
             lat.init_state("boltzmann")

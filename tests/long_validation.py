@@ -133,7 +133,8 @@ def case_batch(steps=20000, sample=8):
     fields = [synth.batch_particle(s) for s in specs]
     lats = []
     for f in fields:
-        lat = Lattice(f.shape_xyz, precision="mixed", n_regions=f.n_regions, max_records=steps + 1)
+        lat = Lattice(f.shape_xyz, precision="mixed", n_regions=f.n_regions, max_records=steps + 1,
+                      batched=True)
         lat.set_fields(f)
         lat.init_state("uniform")
         lats.append(lat)

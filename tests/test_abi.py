@@ -77,7 +77,7 @@ def test_footprint_byte_model(lib):
 
 @pytest.mark.parametrize("field,value", [
     ("p_hop", 0.2), ("p_hop", -0.01), ("n_regions", 0), ("n_regions", 9), ("max_records", 0),
-    ("precision", 5), ("track", 8), ("dt_s", 0.0), ("options", 2), ("conservation_tol", -1.0),
+    ("precision", 5), ("track", 8), ("dt_s", 0.0), ("options", 4), ("conservation_tol", -1.0),
 ])
 def test_config_rejected(lib, field, value):
     st, _ = _footprint(_cfg(8, **{field: value}))

@@ -32,7 +32,7 @@ def test_served_equals_alone_and_oracle(oracle):
         f = j.fields
         nz, ny, nx = f.F.shape
         with Lattice((nx, ny, nz), precision="mixed", track=("fid",), n_regions=f.n_regions,
-                     max_records=j.n_steps + 1) as lat:
+                     max_records=j.n_steps + 1, batched=True) as lat:
             lat.set_fields(f)
             lat.init_state("uniform")
             lat.run(j.n_steps)

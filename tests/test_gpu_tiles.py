@@ -128,15 +128,41 @@ def test_linear_tile_choice_and_limits():
         assert e.value.status == N.LPC_ERR_ARG
 
 
+def test_batched_lattices_plan_longer_z_chunks():
+    """LPC_OPT_BATCHED: automatic plans keep z-chunks of at least 16 planes (or the whole
+    axis); the step is the same (state bits equal to the default plan's)."""
+    from paper_2603_22553_amd.lattice import Lattice
+    f = synth.random_fields((40, 40, 64), seed=77, n_regions=2)
+    out = {}
+    for batched in (False, True):
+        with Lattice(f.shape_xyz, n_regions=2, max_records=41, batched=batched) as lat:
+            out[batched] = lat.plan["zc"]
+            lat.set_fields(f)
+            lat.init_state()
+            lat.run(40)
+            rec = lat.records()
+            blob = lat.save_state()
+            out[(batched, "state")] = blob[:len(blob) - rec.size * 8]
+            out[(batched, "rec")] = rec
+    assert out[True] >= 16 and out[False] < 16
+    assert out[(True, "state")] == out[(False, "state")]
+    assert np.max(np.abs(out[(True, "rec")] - out[(False, "rec")])) <= \
+        1e-12 * np.max(np.abs(out[(False, "rec")]))
+    with Lattice((8, 8, 9), n_regions=2, max_records=2, batched=True) as lat:
+        assert lat.plan["zc"] == 9
+
+
 def test_batch_mixing_linear_and_block_tiles_is_bitwise_solo():
     """A batch steps linear- and block-tiled lattices in one launch per tile kind; each
     ends as if run alone."""
     from paper_2603_22553_amd.lattice import Batch, Lattice
     shapes = [(37, 11, 9), (70, 20, 33), (24, 24, 10), (128, 3, 4)]
     fields = [synth.random_fields(s, seed=400 + k, n_regions=2) for k, s in enumerate(shapes)]
+    batched = [False, True, False, True]        # default and batch-planned lattices mixed
     solo = []
-    for f in fields:
-        with Lattice(f.shape_xyz, precision="mixed", n_regions=2, max_records=61) as lat:
+    for f, bt in zip(fields, batched):
+        with Lattice(f.shape_xyz, precision="mixed", n_regions=2, max_records=61,
+                     batched=bt) as lat:
             lat.set_fields(f)
             lat.init_state()
             lat.run(60)
@@ -144,8 +170,9 @@ def test_batch_mixing_linear_and_block_tiles_is_bitwise_solo():
     assert {p for p, _, _ in solo} >= {1, 64}
     lats = []
     try:
-        for f in fields:
-            lat = Lattice(f.shape_xyz, precision="mixed", n_regions=2, max_records=61)
+        for f, bt in zip(fields, batched):
+            lat = Lattice(f.shape_xyz, precision="mixed", n_regions=2, max_records=61,
+                          batched=bt)
             lats.append(lat)
             lat.set_fields(f)
             lat.init_state()
