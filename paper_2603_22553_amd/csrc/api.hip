@@ -161,6 +161,8 @@ struct SoloTables {
     int64_t prefix[2];
     lpc::FinalizeItem fin;
     int64_t kprefix[2];
+    lpc::SweepItem eq_item;      // the population-only sweep of lpc_equilibrate
+    int64_t eq_prefix[2];
 };
 
 // Buffer placement for cfg. The sweep plan depends on the device (resident workgroups per
@@ -230,6 +232,10 @@ struct lpc_lattice {
     double Fmid = 0.0;                        // centre of the accessible free energies
     int64_t n_open = 0;                       // accessible sites (F < +inf)
     double ghost[kGhostValues] = {};          // host copy of the reservoir ghost table
+    // Plan of the population-only sweeps of lpc_equilibrate: made for that kernel's own
+    // occupancy (it keeps more workgroups resident than the full sweep) and tile limits.
+    // Their partial sums are discarded, so the plan fixes no result.
+    lpc::SweepPlan eq_plan{};
     int occupancy = 1, cus = 1;      // resident sweep workgroups per CU, compute units
 
     template <typename T = void>
@@ -298,7 +304,7 @@ lpc_status use_device(const lpc_lattice *lat)
 
 // Uploads the one-entry work list of lpc_run (plan and step arguments) after anything it
 // holds has changed. The lattice's stream must be idle.
-lpc_status upload_solo(lpc_lattice *lat)
+SoloTables solo_tables(const lpc_lattice *lat)
 {
     SoloTables tables{};
     tables.item = lat->sweep_item(0);
@@ -307,6 +313,16 @@ lpc_status upload_solo(lpc_lattice *lat)
     tables.fin = lat->finalize_item(0);
     tables.kprefix[0] = 0;
     tables.kprefix[1] = lat->L.K;
+    tables.eq_item = tables.item;
+    tables.eq_item.plan = lat->eq_plan;
+    tables.eq_prefix[0] = 0;
+    tables.eq_prefix[1] = lat->eq_plan.nblocks;
+    return tables;
+}
+
+lpc_status upload_solo(lpc_lattice *lat)
+{
+    const SoloTables tables = solo_tables(lat);
     LPC_HIP(hipMemcpy(lat->solo(), &tables, sizeof tables, hipMemcpyHostToDevice));
     return LPC_OK;
 }
@@ -485,6 +501,11 @@ lpc_status lpc_create(const lpc_config *cfg, void *arena, size_t arena_bytes, vo
         lat->L.plan = lpc::make_plan(g, occ, cus, 0,
                                      lpc::linear_tile_max_nx(cfg->precision, variant_of(*cfg)),
                                      zc_floor(*cfg));
+        const uint32_t pop = variant_of(*cfg) & ~uint32_t(LPC_TRACK_FID | LPC_TRACK_MSD);
+        lat->eq_plan = lpc::make_plan(g, lpc::sweep_blocks_per_cu(cfg->precision, pop,
+                                                                 cfg->n_regions),
+                                      cus, 0, lpc::linear_tile_max_nx(cfg->precision, pop),
+                                      zc_floor(*cfg));
         set_chunk(lat->L);
     }
     for (int b = 0; b < 2; ++b) {
@@ -498,13 +519,7 @@ lpc_status lpc_create(const lpc_config *cfg, void *arena, size_t arena_bytes, vo
         }
     }
     const size_t ns = size_t(L.n) * L.storage;
-    SoloTables tables{};
-    tables.item = lat->sweep_item(0);
-    tables.prefix[0] = 0;
-    tables.prefix[1] = lat->L.plan.nblocks;
-    tables.fin = lat->finalize_item(0);
-    tables.kprefix[0] = 0;
-    tables.kprefix[1] = lat->L.K;
+    const SoloTables tables = solo_tables(lat);
     hipError_t e = hipMemcpy(lat->solo(), &tables, sizeof tables, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemsetAsync(lat->at(L.off_F), 0, ns, lat->stream);
@@ -759,7 +774,8 @@ lpc_status lpc_equilibrate(lpc_lattice *lat, int64_t max_steps, double tol, int6
     if (lpc_status s = use_device(lat))
         return s;
     SoloTables *t = lat->solo();
-    lpc::StepList list{&t->item, t->prefix, 1, lat->L.plan.tx, lat->L.plan.nblocks, 0, 0};
+    lpc::StepList list{&t->eq_item, t->eq_prefix, 1, lat->eq_plan.tx, lat->eq_plan.nblocks, 0,
+                       0};
     // workgroup maxima in the per-step partial sums (population-only steps discard theirs,
     // and stream order puts each check between the steps): enough workgroups to stream
     // both population buffers at full bandwidth
