@@ -179,6 +179,18 @@ def workload_particle(args):
             "peak_ppm_diff": float(abs(m["peak_ppm"] - a["peak_ppm"])),
             "D_max_rel": float(np.max(np.abs(np.asarray(m["D"]) - a["D"]) / np.abs(a["D"]))),
             "steps": args.steps + args.warmup}
+    if args.calibrate:
+        # achievable ceilings measured in the same run: a plain copy, and the sweep's own
+        # column pattern without its halo and arithmetic (FP64 full path)
+        cp, col = copy_rate(10), columns_rate(10)
+        cal = {"copy_GBps": round(cp, 1), "sweep_pattern_GBps": round(col, 1),
+               "sweep_pattern_frac_of_peak": round(col / HBM_PEAK_GBS, 4)}
+        if head == "fp64":
+            cal["algorithmic_frac_of_pattern"] = round(line["roofline"]["achieved"] / col, 4)
+            tr = line["roofline"]["traffic"]
+            if tr:
+                cal["counter_traffic_frac_of_pattern"] = round(tr / (ms_step * 1e-3) / 1e9 / col, 4)
+        line["calibration"] = cal
     if args.cpu_steps > 0:
         line["cpu_baseline"] = cpu_baseline(f, args.cpu_steps)
     return line
@@ -504,9 +516,8 @@ def workload_serve(args):
 
 # ------------------------------------------------------------------- copy calibration
 
-def workload_copy(args):
-    """Plain device copy (lpc_stream_copy) of 1 GiB: achievable HBM bandwidth, and the kernel of
-    known traffic that scales the FETCH_SIZE / WRITE_SIZE counters."""
+def copy_rate(steps):
+    """GB/s (read + write) of lpc_stream_copy over 1 GiB, `steps` copies timed."""
     import ctypes
     import torch
     from paper_2603_22553_amd import _native as N
@@ -516,33 +527,49 @@ def workload_copy(args):
     s = torch.cuda.current_stream()
 
     def copy():
-        for _ in range(args.steps):
+        for _ in range(steps):
             N.call("lpc_stream_copy", ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
                    n, ctypes.c_void_p(s.cuda_stream))
 
     timed(s, copy)
     _, ms = timed(s, copy)
     assert bool(torch.equal(a[:4096], b[:4096]))
-    gbs = 2 * n * args.steps / (ms * 1e-3) / 1e9
-    del a, b
-    # the FP64 full sweep's column streams on the 256^3 lattice, without its arithmetic
+    return 2 * n * steps / (ms * 1e-3) / 1e9
+
+
+def columns_rate(steps):
+    """GB/s of lpc_stream_columns on 256^3: the FP64 full sweep's column streams (12 reads
+    and 9 writes of doubles per site, 64 x 4 tiles, z-chunks of 128) without its halo and
+    arithmetic."""
+    import ctypes
+    import torch
+    from paper_2603_22553_amd import _native as N
     side, zc = 256, 128
     sites = side ** 3
     buf = torch.rand(21 * sites, dtype=torch.float64, device="cuda")
     arr = [buf[k * sites:(k + 1) * sites] for k in range(21)]
     ins = (ctypes.c_void_p * 12)(*[t.data_ptr() for t in arr[:12]])
     outs = (ctypes.c_void_p * 9)(*[t.data_ptr() for t in arr[12:]])
+    s = torch.cuda.current_stream()
 
     def columns():
-        for _ in range(args.steps):
+        for _ in range(steps):
             N.call("lpc_stream_columns", ins, outs, side, side, side, zc,
                    ctypes.c_void_p(s.cuda_stream))
 
     timed(s, columns)
-    _, ms_c = timed(s, columns)
+    _, ms = timed(s, columns)
     assert bool(torch.allclose(arr[12][:4096], arr[0][:4096] + (arr[9][:4096]
                                + arr[10][:4096] * arr[11][:4096]), rtol=1e-15, atol=0.0))
-    gbs_c = 21 * 8 * sites * args.steps / (ms_c * 1e-3) / 1e9
+    return 21 * 8 * sites * steps / (ms * 1e-3) / 1e9
+
+
+def workload_copy(args):
+    """Plain device copy (lpc_stream_copy) of 1 GiB: achievable HBM bandwidth, and the kernel of
+    known traffic that scales the FETCH_SIZE / WRITE_SIZE counters; then the sweep's own
+    column pattern (lpc_stream_columns)."""
+    gbs = copy_rate(args.steps)
+    gbs_c = columns_rate(args.steps)
     return {"metric": "device copy bandwidth (read + write)", "value": round(gbs, 1),
             "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
@@ -564,6 +591,9 @@ def main():
                                            "equilibrate", "porous", "supercap"],
                     default="particle")
     ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both")
+    ap.add_argument("--calibrate", type=int, default=1,
+                    help="particle workload: also time a plain copy and the sweep's column "
+                         "pattern (achievable ceilings) and report them beside the roofline")
     ap.add_argument("--cpu-steps", type=int, default=20,
                     help="oracle steps timed for the CPU baseline (0 skips it)")
     ap.add_argument("--batch-count", type=int, default=512)
