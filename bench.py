@@ -182,9 +182,13 @@ def workload_particle(args):
     if args.calibrate:
         # achievable ceilings measured in the same run: a plain copy, and the sweep's own
         # column pattern without its halo and arithmetic (FP64 full path)
-        cp, col = copy_rate(10), columns_rate(10)
+        cp, col, colm = copy_rate(10), columns_rate(10), columns_mixed_rate(10)
         cal = {"copy_GBps": round(cp, 1), "sweep_pattern_GBps": round(col, 1),
-               "sweep_pattern_frac_of_peak": round(col / HBM_PEAK_GBS, 4)}
+               "sweep_pattern_frac_of_peak": round(col / HBM_PEAK_GBS, 4),
+               "mixed_sweep_pattern_GBps": round(colm, 1)}
+        if "mixed" in line:
+            cal["mixed_algorithmic_frac_of_pattern"] = round(
+                line["mixed"]["roofline"]["achieved"] / colm, 4)
         if head == "fp64":
             cal["algorithmic_frac_of_pattern"] = round(line["roofline"]["achieved"] / col, 4)
             tr = line["roofline"]["traffic"]
@@ -564,12 +568,43 @@ def columns_rate(steps):
     return 21 * 8 * sites * steps / (ms * 1e-3) / 1e9
 
 
+def columns_mixed_rate(steps):
+    """GB/s of lpc_stream_columns_mixed on 256^3: the mixed full sweep's column streams
+    (population in double, 10 floats and the region byte read; 9 arrays written; 89 B per
+    site) without its halo and arithmetic."""
+    import ctypes
+    import torch
+    from paper_2603_22553_amd import _native as N
+    side, zc = 256, 128
+    sites = side ** 3
+    rho = torch.rand(2 * sites, dtype=torch.float64, device="cuda")
+    flt = torch.rand(18 * sites, dtype=torch.float32, device="cuda")
+    reg = torch.randint(0, 2, (sites,), dtype=torch.uint8, device="cuda")
+    f = [flt[k * sites:(k + 1) * sites] for k in range(18)]
+    ins = (ctypes.c_void_p * 10)(*[t.data_ptr() for t in f[:10]])
+    outs = (ctypes.c_void_p * 8)(*[t.data_ptr() for t in f[10:]])
+    s = torch.cuda.current_stream()
+
+    def columns():
+        for _ in range(steps):
+            N.call("lpc_stream_columns_mixed", ctypes.c_void_p(rho.data_ptr()), ins,
+                   ctypes.c_void_p(reg.data_ptr()), ctypes.c_void_p(rho[sites:].data_ptr()), outs,
+                   side, side, side, zc, ctypes.c_void_p(s.cuda_stream))
+
+    timed(s, columns)
+    _, ms = timed(s, columns)
+    e = f[8][:4096] + f[9][:4096] * reg[:4096].float()
+    assert bool(torch.allclose(f[10][:4096], f[0][:4096] + e, rtol=1e-6, atol=0.0))
+    return 89 * sites * steps / (ms * 1e-3) / 1e9
+
+
 def workload_copy(args):
     """Plain device copy (lpc_stream_copy) of 1 GiB: achievable HBM bandwidth, and the kernel of
     known traffic that scales the FETCH_SIZE / WRITE_SIZE counters; then the sweep's own
     column pattern (lpc_stream_columns)."""
     gbs = copy_rate(args.steps)
     gbs_c = columns_rate(args.steps)
+    gbs_m = columns_mixed_rate(args.steps)
     return {"metric": "device copy bandwidth (read + write)", "value": round(gbs, 1),
             "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
@@ -579,7 +614,12 @@ def workload_copy(args):
                               "frac_of_copy": round(gbs_c / gbs, 4),
                               "what": "lpc_stream_columns on 256^3: the FP64 sweep's 12 column "
                                       "reads and 9 writes per site, 64x4 tiles, zc 128, "
-                                      "no halo, no arithmetic"}}
+                                      "no halo, no arithmetic"},
+            "sweep_pattern_mixed": {"GBps": round(gbs_m, 1),
+                                    "frac_of_peak": round(gbs_m / HBM_PEAK_GBS, 4),
+                                    "frac_of_copy": round(gbs_m / gbs, 4),
+                                    "what": "lpc_stream_columns_mixed on 256^3: the mixed "
+                                            "sweep's column streams, 89 B per site"}}
 
 
 def main():

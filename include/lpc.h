@@ -277,6 +277,16 @@ lpc_status lpc_stream_copy(const void *src, void *dst, size_t bytes, void *strea
 lpc_status lpc_stream_columns(const double *const *in, double *const *out, int32_t nx,
                               int32_t ny, int32_t nz, int32_t zc, void *stream);
 
+/* Calibration utility: the same for the mixed path with FID and moments. Reads rho_in
+ * (doubles), in[0..9] (floats: 8 state arrays, free energy, shift) and region (bytes);
+ * writes rho_out (doubles) and out[0..7] (floats); nx * ny * nz values each, outputs
+ * overlapping no array. e = in[8] + in[9] * region (float); rho_out = rho_in + e and
+ * out[k] = in[k] + e. Bytes moved are 89 * nx * ny * nz, the mixed sweep's algorithmic
+ * count. Errors and stream as for lpc_stream_columns. */
+lpc_status lpc_stream_columns_mixed(const double *rho_in, const float *const *in,
+                                    const uint8_t *region, double *rho_out, float *const *out,
+                                    int32_t nx, int32_t ny, int32_t nz, int32_t zc, void *stream);
+
 /* tile_x of lpc_set_plan for linear tiles: each workgroup takes 256 consecutive sites of
  * the x-y plane (x fastest) instead of a block of columns, so a narrow lattice leaves
  * almost no lane idle. Available up to an nx that depends on the precision and track set

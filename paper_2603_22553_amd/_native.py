@@ -85,6 +85,7 @@ SIGNATURES = {
     "lpc_load_state": [_P, _P, _SZ],
     "lpc_stream_copy": [_P, _P, _SZ, _P],
     "lpc_stream_columns": [_P, _P, _I32, _I32, _I32, _I32, _P],
+    "lpc_stream_columns_mixed": [_P, _P, _P, _P, _P, _I32, _I32, _I32, _I32, _P],
     "lpc_describe": [_P, ctypes.c_char_p, _SZ],
     "lpc_set_plan": [_P, _I32, _I32],
     "lpc_spectrum_length": [_P, _PI64],

@@ -306,6 +306,58 @@ int grid_for(int64_t n)
     return static_cast<int>(g < 1 ? 1 : (g > 4096 ? 4096 : g));
 }
 
+// The mixed full sweep's memory pattern without its arithmetic: 64 x 4 blocks of columns
+// marching runs of z-planes, each thread reading its column's population (double), 10
+// floats and the region byte one plane ahead and writing the population and 8 floats past
+// the caches, one barrier per plane. 89 bytes per site, as the sweep's algorithmic count.
+__global__ __launch_bounds__(kThreads, 2) void k_stream_columns_mixed(MixedColumns c, int nx,
+                                                                      int ny, int nz, int zc,
+                                                                      int tiles_x, int tiles_y)
+{
+    constexpr int TX = 64, TY = kThreads / TX;
+    const int t = static_cast<int>(threadIdx.x);
+    const int tiles = tiles_x * tiles_y;
+    const int tile = static_cast<int>(blockIdx.x % tiles);
+    const int chunk = static_cast<int>(blockIdx.x / tiles);
+    const int x = (tile % tiles_x) * TX + t % TX, y = (tile / tiles_x) * TY + t / TX;
+    const int z0 = chunk * zc, z1 = min(nz, z0 + zc);
+    const bool act = x < nx && y < ny;
+    const int64_t plane = static_cast<int64_t>(nx) * ny, col = x + static_cast<int64_t>(nx) * y;
+    struct Site {
+        double rho;
+        float v[kMixedIn];
+        uint8_t r;
+    } w[2];
+    auto load = [&](Site &d, int z) {
+        const bool on = act && z < z1;
+        const int64_t i = plane * z + col;
+        d.rho = on ? c.rho_in[i] : 0.0;
+#pragma unroll
+        for (int k = 0; k < kMixedIn; ++k)
+            d.v[k] = on ? c.in[k][i] : 0.0f;
+        d.r = on ? c.region[i] : uint8_t(0);
+    };
+    auto store = [&](const Site &d, int z) {
+        if (!(act && z < z1))
+            return;
+        const int64_t i = plane * z + col;
+        const float e = d.v[kMixedOut] + d.v[kMixedOut + 1] * static_cast<float>(d.r);
+        __builtin_nontemporal_store(d.rho + e, c.rho_out + i);
+#pragma unroll
+        for (int k = 0; k < kMixedOut; ++k)
+            __builtin_nontemporal_store(d.v[k] + e, c.out[k] + i);
+    };
+    load(w[0], z0);
+    for (int z = z0; z < z1; z += 2) {
+        load(w[1], z + 1);
+        __syncthreads();
+        store(w[0], z);
+        load(w[0], z + 2);
+        __syncthreads();
+        store(w[1], z + 1);
+    }
+}
+
 }  // namespace
 
 hipError_t launch_fid_spectrum(const double *records, int64_t rows, int32_t K, int32_t R,
@@ -348,6 +400,16 @@ hipError_t launch_region_sums(int32_t precision, const StateView &st, const uint
 {
     return precision == 0 ? region_sums_typed<double>(st, region, n, R, part, nparts, s)
                           : region_sums_typed<float>(st, region, n, R, part, nparts, s);
+}
+
+hipError_t launch_stream_columns_mixed(const MixedColumns &c, int32_t nx, int32_t ny, int32_t nz,
+                                       int32_t zc, hipStream_t s)
+{
+    const int tiles_x = (nx + 63) / 64, tiles_y = (ny + 3) / 4;
+    const int64_t blocks = int64_t(tiles_x) * tiles_y * ((nz + zc - 1) / zc);
+    hipLaunchKernelGGL(k_stream_columns_mixed, dim3(static_cast<unsigned>(blocks)), dim3(kThreads),
+                       0, s, c, nx, ny, nz, zc, tiles_x, tiles_y);
+    return hipGetLastError();
 }
 
 hipError_t launch_profile(const double *rho, const Geometry &g, int32_t axis, double *profile,

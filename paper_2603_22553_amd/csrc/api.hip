@@ -1617,6 +1617,56 @@ lpc_status lpc_stream_columns(const double *const *in, double *const *out, int32
     return ok();
 }
 
+lpc_status lpc_stream_columns_mixed(const double *rho_in, const float *const *in,
+                                    const uint8_t *region, double *rho_out, float *const *out,
+                                    int32_t nx, int32_t ny, int32_t nz, int32_t zc, void *stream)
+{
+    if (!rho_in || !in || !region || !rho_out || !out)
+        return fail(LPC_ERR_ARG, "NULL array");
+    if (nx < 1 || ny < 1 || nz < 1 || zc < 1)
+        return fail(LPC_ERR_ARG, "sizes and zc must be >= 1");
+    const int64_t n = int64_t(nx) * ny * nz;
+    const int64_t blocks = int64_t((nx + 63) / 64) * ((ny + 3) / 4) * ((nz + zc - 1) / zc);
+    if (blocks > INT32_MAX)
+        return fail(LPC_ERR_ARG, "too many workgroups; raise zc");
+    lpc::MixedColumns c{};
+    c.rho_in = rho_in;
+    c.region = region;
+    c.rho_out = rho_out;
+    // every array with its size; the outputs (the last 9) overlap nothing
+    struct Span {
+        const void *p;
+        size_t bytes;
+    };
+    Span spans[2 + lpc::kMixedIn + 1 + lpc::kMixedOut];
+    int ns = 0;
+    spans[ns++] = {rho_in, size_t(n) * 8};
+    for (int k = 0; k < lpc::kMixedIn; ++k) {
+        if (!in[k])
+            return fail(LPC_ERR_ARG, "input array %d is NULL", k);
+        c.in[k] = in[k];
+        spans[ns++] = {in[k], size_t(n) * 4};
+    }
+    spans[ns++] = {region, size_t(n)};
+    const int first_out = ns;
+    spans[ns++] = {rho_out, size_t(n) * 8};
+    for (int k = 0; k < lpc::kMixedOut; ++k) {
+        if (!out[k])
+            return fail(LPC_ERR_ARG, "output array %d is NULL", k);
+        c.out[k] = out[k];
+        spans[ns++] = {out[k], size_t(n) * 4};
+    }
+    for (int a = first_out; a < ns; ++a)
+        for (int b = 0; b < a; ++b) {
+            const char *p = static_cast<const char *>(spans[a].p);
+            const char *q = static_cast<const char *>(spans[b].p);
+            if (p < q + spans[b].bytes && q < p + spans[a].bytes)
+                return fail(LPC_ERR_ARG, "output array %d overlaps array %d", a, b);
+        }
+    LPC_HIP(lpc::launch_stream_columns_mixed(c, nx, ny, nz, zc, static_cast<hipStream_t>(stream)));
+    return ok();
+}
+
 lpc_status lpc_set_plan(lpc_lattice *lat, int32_t tile_x, int32_t zc)
 {
     if (!lat)

@@ -177,4 +177,18 @@ struct ColumnArrays {
 hipError_t launch_stream_columns(const ColumnArrays &c, int32_t nx, int32_t ny, int32_t nz,
                                  int32_t zc, hipStream_t s);
 
+// The mixed full sweep's column streams without its arithmetic (calibration kernel): the
+// population in double, 10 float arrays (8 state, free energy, shift) and the region byte
+// read; the population and the 8 float state arrays written.
+constexpr int kMixedIn = 10, kMixedOut = 8;
+struct MixedColumns {
+    const double *rho_in;
+    const float *in[kMixedIn];
+    const uint8_t *region;
+    double *rho_out;
+    float *out[kMixedOut];
+};
+hipError_t launch_stream_columns_mixed(const MixedColumns &c, int32_t nx, int32_t ny, int32_t nz,
+                                       int32_t zc, hipStream_t s);
+
 }  // namespace lpc

@@ -230,3 +230,33 @@ def test_stream_columns_calibration():
     with pytest.raises(N.LpcError) as err:
         N.call("lpc_stream_columns", ins, outs, *shape, 0, ctypes.c_void_p(s.cuda_stream))
     assert err.value.status == N.LPC_ERR_ARG
+
+
+def test_stream_columns_mixed_calibration():
+    """lpc_stream_columns_mixed computes rho_out = rho_in + e and out[k] = in[k] + e with
+    e = in[8] + in[9] * region on a ragged lattice, and rejects overlapping outputs."""
+    import ctypes
+    shape = (70, 9, 13)
+    n = shape[0] * shape[1] * shape[2]
+    rho = torch.rand(2 * n, dtype=torch.float64, device="cuda")
+    flt = torch.rand(18 * n, dtype=torch.float32, device="cuda")
+    reg = torch.randint(0, 3, (n,), dtype=torch.uint8, device="cuda")
+    f = [flt[k * n:(k + 1) * n] for k in range(18)]
+    ins = (ctypes.c_void_p * 10)(*[t.data_ptr() for t in f[:10]])
+    outs = (ctypes.c_void_p * 8)(*[t.data_ptr() for t in f[10:]])
+    s = torch.cuda.current_stream()
+    args = (ctypes.c_void_p(rho.data_ptr()), ins, ctypes.c_void_p(reg.data_ptr()),
+            ctypes.c_void_p(rho[n:].data_ptr()), outs, *shape, 5, ctypes.c_void_p(s.cuda_stream))
+    N.call("lpc_stream_columns_mixed", *args)
+    s.synchronize()
+    e = f[8].cpu().numpy() + f[9].cpu().numpy() * reg.cpu().numpy().astype(np.float32)
+    r = rho.cpu().numpy()
+    # e is a float that the kernel may form with one fused rounding
+    assert np.allclose(r[n:], r[:n] + e.astype(np.float64), rtol=1e-6, atol=0.0)
+    for k in range(8):
+        assert np.allclose(f[10 + k].cpu().numpy(), f[k].cpu().numpy() + e, rtol=1e-6, atol=0.0)
+    bad = (ctypes.c_void_p * 8)(*[f[10].data_ptr()] * 8)
+    with pytest.raises(N.LpcError) as err:
+        N.call("lpc_stream_columns_mixed", args[0], ins, args[2], args[3], bad, *shape, 5,
+               ctypes.c_void_p(s.cuda_stream))
+    assert err.value.status == N.LPC_ERR_ARG
