@@ -107,30 +107,33 @@ def run_particle(f, precision, steps, warmup, track=("fid", "msd")):
     lat.run(warmup)
     lat.synchronize()
 
+    msd = "msd" in track
+
     def work():
         lat.run(steps)
-        return lat.peak_ppm(), lat.diffusion()
+        return lat.peak_ppm(), (lat.diffusion() if msd else (None, None))
 
     (peak, (D, ratio)), ms = timed(lat.stream, work)
     lat.check()                    # finite FID, population conserved to 1e-12
     mass = lat.moments()[0]
     out = {"ms": ms, "gsu_s": f.n_sites * steps / (ms * 1e-3) / 1e9,
            "mass_drift": float(abs(mass[-1] / mass[0] - 1.0)), "peak_ppm": peak,
-           "D_over_Dbulk": [round(float(v), 6) for v in ratio], "D": D, "plan": lat.describe(),
-           "fid": lat.fid(), "uptake": lat.uptake()[-1]}
+           "D_over_Dbulk": [round(float(v), 6) for v in ratio] if msd else None, "D": D,
+           "plan": lat.describe(), "fid": lat.fid(), "uptake": lat.uptake()[-1]}
     lat.close()
     return out
 
 
-def cpu_baseline(f, steps):
+def cpu_baseline(f, steps, moments=True):
     from oracle import oracle
     oracle.build(force=False)
     t = time.perf_counter()
-    oracle.run(f.F, f.delta, f.region, f.n_regions, steps)
+    oracle.run(f.F, f.delta, f.region, f.n_regions, steps, moments=moments)
     dt = time.perf_counter() - t
+    what = "FID + MSD" if moments else "FID only"
     return {"value": round(f.n_sites * steps / dt / 1e9, 5), "unit": "GSU/s",
             "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"{steps} steps of the same 256^3 particle lattice (FP64, FID + MSD, "
+            "sample": f"{steps} steps of the same 256^3 particle lattice (FP64, {what}, "
                       f"{f.n_sites * steps:.3g} site-updates), {dt:.1f} s"}
 
 
@@ -138,9 +141,11 @@ def workload_particle(args):
     from paper_2603_22553_amd import synth
     f = synth.single_particle_large()
     precisions = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    track = tuple(args.track.split("+"))
+    full = track == ("fid", "msd")
     res = {}
     for p in precisions:
-        res[p] = run_particle(f, p, args.steps, args.warmup)
+        res[p] = run_particle(f, p, args.steps, args.warmup, track)
         print(f"# {p}: {res[p]['gsu_s']:.2f} GSU/s, {res[p]['ms'] / args.steps:.4f} ms/step, "
               f"{res[p]['plan']}", file=sys.stderr, flush=True)
     head = "fp64" if "fp64" in res else precisions[0]
@@ -152,10 +157,11 @@ def workload_particle(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if head == "fp64" else "f32-storage/f64-sums", "data": "synthetic",
         "config": {"workload": "single large particle: 256^3 periodic box, radius-112 carbon "
-                               "particle, FID + MSD recorded every step",
+                               "particle, " + ("FID + MSD" if full else "FID only")
+                               + " recorded every step",
                    "sites": f.n_sites, "regions": f.n_regions, "precision": head,
                    "steps_per_pass": 1, "plan": r["plan"]},
-        "roofline": roofline(f.n_sites, head, ms_step, measured=True),
+        "roofline": roofline(f.n_sites, head, ms_step, track=track, measured=full),
         "results": {"mass_drift": r["mass_drift"], "peak_ppm": round(r["peak_ppm"], 5),
                     "D_over_Dbulk": r["D_over_Dbulk"]},
     }
@@ -165,7 +171,7 @@ def workload_particle(args):
         ms_p = rr["ms"] / args.steps
         line[p] = {"value": round(rr["gsu_s"], 4), "unit": "GSU/s", "ms_per_step": round(ms_p, 6),
                    "dtype": "f32-storage/f64-sums",
-                   "roofline": roofline(f.n_sites, p, ms_p, measured=True),
+                   "roofline": roofline(f.n_sites, p, ms_p, track=track, measured=full),
                    "results": {"mass_drift": rr["mass_drift"], "peak_ppm": round(rr["peak_ppm"], 5),
                                "D_over_Dbulk": rr["D_over_Dbulk"]}}
     if "fp64" in res and "mixed" in res:
@@ -177,9 +183,10 @@ def workload_particle(args):
             "fid_rel_l2": float(np.linalg.norm(m["fid"] - a["fid"]) / np.linalg.norm(a["fid"])),
             "uptake_max_rel": float(np.max(np.abs(m["uptake"] - a["uptake"]) / np.abs(a["uptake"]))),
             "peak_ppm_diff": float(abs(m["peak_ppm"] - a["peak_ppm"])),
-            "D_max_rel": float(np.max(np.abs(np.asarray(m["D"]) - a["D"]) / np.abs(a["D"]))),
+            "D_max_rel": (float(np.max(np.abs(np.asarray(m["D"]) - a["D"]) / np.abs(a["D"])))
+                          if full else None),
             "steps": args.steps + args.warmup}
-    if args.calibrate:
+    if args.calibrate and full:
         # achievable ceilings measured in the same run: a plain copy, and the sweep's own
         # column pattern without its halo and arithmetic (FP64 full path)
         cp, col, colm = copy_rate(10), columns_rate(10), columns_mixed_rate(10)
@@ -196,7 +203,7 @@ def workload_particle(args):
                 cal["counter_traffic_frac_of_pattern"] = round(tr / (ms_step * 1e-3) / 1e9 / col, 4)
         line["calibration"] = cal
     if args.cpu_steps > 0:
-        line["cpu_baseline"] = cpu_baseline(f, args.cpu_steps)
+        line["cpu_baseline"] = cpu_baseline(f, args.cpu_steps, moments=full)
     return line
 
 
@@ -631,6 +638,8 @@ def main():
                                            "equilibrate", "porous", "supercap"],
                     default="particle")
     ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both")
+    ap.add_argument("--track", choices=["fid+msd", "fid"], default="fid+msd",
+                    help="particle workload: recorded quantities (fid: the serving kernel)")
     ap.add_argument("--calibrate", type=int, default=1,
                     help="particle workload: also time a plain copy and the sweep's column "
                          "pattern (achievable ceilings) and report them beside the roofline")
