@@ -294,6 +294,12 @@ lpc_status lpc_stream_columns_mixed(const double *rho_in, const float *const *in
  * reservoir axis. */
 #define LPC_TILE_LINEAR 1
 
+/* Widest x extent (nx) that lattices of this configuration's precision, track set and
+ * variant can run on linear tiles, in *max_nx (0: none; lattices with a mobility field or a
+ * reservoir axis run block tiles only). Host-only: needs no device. LPC_ERR_ARG for an
+ * invalid configuration or NULL max_nx. */
+lpc_status lpc_query_linear_tiles(const lpc_config *cfg, int32_t *max_nx);
+
 /* Overrides the launch plan of the sweep: tile_x 64, 32 or 16 columns per tile row,
  * LPC_TILE_LINEAR, or 0 (automatic: the block width with the least padding in x within
  * 1.5x, or linear tiles where they leave fewer lanes idle and are available), and zc planes

@@ -84,6 +84,7 @@ SIGNATURES = {
     "lpc_save_state": [_P, _P, _SZ, _PSZ],
     "lpc_load_state": [_P, _P, _SZ],
     "lpc_stream_copy": [_P, _P, _SZ, _P],
+    "lpc_query_linear_tiles": [_P, _P],
     "lpc_stream_columns": [_P, _P, _I32, _I32, _I32, _I32, _P],
     "lpc_stream_columns_mixed": [_P, _P, _P, _P, _P, _I32, _I32, _I32, _I32, _P],
     "lpc_describe": [_P, ctypes.c_char_p, _SZ],

@@ -65,14 +65,11 @@ def candidates(shape_xyz, auto_zc: int, linear: bool = True):
 
 
 def _takes_linear(lat) -> bool:
-    """Whether the lattice's sweep variant runs linear tiles at its width (the library
-    refuses the plan otherwise); leaves the lattice on its automatic plan."""
-    try:
-        lat.set_plan(LINEAR, 0)
-    except L.LpcError:
-        return False
-    lat.set_plan(0, 0)
-    return True
+    """Whether the lattice's sweep variant runs linear tiles at its width."""
+    import ctypes
+    widest = ctypes.c_int32()
+    L.N.call("lpc_query_linear_tiles", ctypes.byref(lat.cfg), ctypes.byref(widest))
+    return lat.shape_xyz[0] <= widest.value
 
 
 def tune(shape_xyz, bc=("periodic",) * 3, precision="fp64", track=("fid", "msd"), n_regions=1,

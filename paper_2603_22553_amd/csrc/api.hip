@@ -467,6 +467,16 @@ lpc_status lpc_query_footprint(const lpc_config *cfg, size_t *bytes)
     return ok();
 }
 
+lpc_status lpc_query_linear_tiles(const lpc_config *cfg, int32_t *max_nx)
+{
+    if (lpc_status s = validate_config(cfg))
+        return s;
+    if (!max_nx)
+        return fail(LPC_ERR_ARG, "max_nx is NULL");
+    *max_nx = lpc::linear_tile_max_nx(cfg->precision, variant_of(*cfg));
+    return ok();
+}
+
 lpc_status lpc_create(const lpc_config *cfg, void *arena, size_t arena_bytes, void *stream,
                       lpc_lattice **out)
 {

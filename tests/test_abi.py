@@ -125,3 +125,26 @@ def test_p_hop_from_residence_time():
     assert mean_steps * 5e-6 == pytest.approx(7e-5, rel=1e-9)
     with pytest.raises(ValueError):
         p_hop_from_residence_time(1e-6, 5e-6)
+
+
+def test_linear_tile_limits(lib):
+    """Widest lattice on linear tiles per variant: the LDS window of 256 + 2 nx cells of a
+    linear tile must leave two workgroups per compute unit (80 KiB each), and 2 nx halo
+    sites must fit 256 threads. FP64 with FID and moments stores 88-byte cells (100 sites);
+    the smaller cells reach the 128-site thread limit; mobility or reservoirs: none."""
+    def limit(**kw):
+        v = ctypes.c_int32(-1)
+        N.call("lpc_query_linear_tiles", ctypes.byref(_cfg(8, **kw)), ctypes.byref(v))
+        return v.value
+    fid, msd = N.TRACK_FID, N.TRACK_MSD
+    assert limit(precision=N.PREC_FP64, track=fid | msd) == 100
+    assert (80 * 1024 - 1024) // 2 // 88 == 459 and (459 - 256) // 2 // 4 * 4 == 100
+    assert limit(precision=N.PREC_MIXED, track=fid | msd) == 128
+    assert limit(precision=N.PREC_FP64, track=fid) == 128
+    assert limit(precision=N.PREC_FP64, track=0) == 128
+    assert limit(precision=N.PREC_MIXED, track=fid | msd, options=N.OPT_MOBILITY) == 0
+    assert limit(precision=N.PREC_FP64, track=fid | msd, options=N.OPT_BATCHED) == 100
+    assert limit(precision=N.PREC_FP64, track=fid, bc=(N.BC_RESERVOIR, 0, 0)) == 0
+    v = ctypes.c_int32()
+    assert N.status("lpc_query_linear_tiles", ctypes.byref(_cfg(8, precision=7)),
+                    ctypes.byref(v)) == N.LPC_ERR_ARG
