@@ -76,6 +76,46 @@ def test_batch_against_oracle(oracle):
         lat.close()
 
 
+def test_batch_full_size_in_bench_configuration(oracle):
+    """The 512-particle batch at full size in the launch configuration the benchmark times
+    (batch plans, linear tiles where they apply, mixed path) over a 4-step prefix: the
+    smallest, the largest and two seeded particles against the oracle, element by element
+    on the populations and on every record."""
+    from paper_2603_22553_amd.lattice import Batch, Lattice
+    specs = synth.batch_specs(512, 2000)
+    fields = [synth.batch_particle(s) for s in specs]
+    radii = [s.radius for s in specs]
+    pick = sorted({int(np.argmin(radii)), int(np.argmax(radii)), 100, 400})
+    steps = 4
+    lats = []
+    try:
+        for f in fields:
+            lat = Lattice(f.shape_xyz, precision="mixed", n_regions=f.n_regions,
+                          max_records=steps + 1, batched=True)
+            lats.append(lat)
+            lat.set_fields(f)
+            lat.init_state("uniform")
+        assert 1 in {lat.plan["tile_x"] for lat in lats}
+        with Batch(lats) as b:
+            b.run(steps)
+        for k in pick:
+            f, lat = fields[k], lats[k]
+            o = oracle.run(f.F, f.delta, f.region, f.n_regions, steps)
+            R = f.n_regions
+            rec = lat.records()
+            G = rec[:, 0:2 * R:2].sum(1) + 1j * rec[:, 1:2 * R:2].sum(1)
+            assert rel_l2(G, o.fid()) <= 1e-3, k
+            U, Uo = rec[:, 2 * R:3 * R], o.records[:, 2 * R:3 * R]
+            assert np.max(np.abs(U - Uo)) <= 1e-5 * np.max(np.abs(Uo)), k
+            S, So = rec[:, 3 * R:], o.records[:, 3 * R:]
+            assert np.max(np.abs(S - So)) <= 1e-4 * max(np.max(np.abs(So)), 1.0), k
+            rho = lat.population().reshape(-1)
+            assert np.max(np.abs(rho - o.rho)) <= 1e-5 * np.max(o.rho), k
+    finally:
+        for lat in lats:
+            lat.close()
+
+
 def test_batch_errors():
     from paper_2603_22553_amd.lattice import Batch
     f = synth.random_fields((8, 8, 8), seed=1)
