@@ -91,3 +91,45 @@ def test_batched_study_equals_solo_runs():
         for part, vals in r["parts"].items():
             for key in ("peak_ppm", "D_over_Dbulk", "uptake"):
                 assert vals[key] == alone["parts"][part][key], (r["kind"], part, key)
+
+
+def test_full_size_study_in_bench_configuration(oracle):
+    """The four 100 x 100 x 300 systems of the study at full size, stepped as one batch in
+    the workflow's launch configuration (batch plans, linear tiles, mixed path, 282 MHz,
+    closed z, p0 from tau = 1 ms), over a 4-step prefix from the Boltzmann start: the film at
+    2 V and the monolith at 0 V against the oracle on populations and every record."""
+    from paper_2603_22553_amd import supercap as S
+    from paper_2603_22553_amd.lattice import Batch, Lattice, p_hop_from_residence_time
+    systems = [S.system(k, v) for k in ("monolith", "film") for v in (0.0, 2.0)]
+    p0 = p_hop_from_residence_time(1e-3, 5e-6)
+    steps = 4
+    lats = []
+    try:
+        for sysm in systems:
+            f = sysm.fields
+            lat = Lattice(f.shape_xyz, bc=("periodic", "periodic", "closed"), precision="mixed",
+                          n_regions=3, p_hop=p0, dt_s=5e-6, larmor_hz=282e6,
+                          max_records=steps + 1, batched=True)
+            lats.append(lat)
+            lat.set_fields(f)
+            lat.init_state("boltzmann")
+        assert all(lat.plan["tile_x"] == 1 for lat in lats)
+        with Batch(lats) as b:
+            b.run(steps)
+        for k in (0, 3):
+            f, lat = systems[k].fields, lats[k]
+            o = oracle.run(f.F, f.delta, f.region, 3, steps, bc=(0, 0, 1), p0=p0, dt=5e-6,
+                           nu0=282e6, init="boltzmann")
+            rec = lat.records()
+            G = rec[:, 0:6:2] + 1j * rec[:, 1:6:2]
+            Go = o.records[:, 0:6:2] + 1j * o.records[:, 1:6:2]
+            assert np.max(np.abs(G - Go)) <= 1e-5 * np.max(np.abs(Go)), k
+            assert np.max(np.abs(rec[:, 6:9] - o.records[:, 6:9])) <= \
+                1e-5 * np.max(np.abs(o.records[:, 6:9])), k
+            S2, S2o = rec[:, 9:], o.records[:, 9:]
+            assert np.max(np.abs(S2 - S2o)) <= 1e-4 * max(np.max(np.abs(S2o[:, 3:])), 1.0), k
+            rho = lat.population().reshape(-1)
+            assert np.max(np.abs(rho - o.rho)) <= 1e-5 * np.max(o.rho), k
+    finally:
+        for lat in lats:
+            lat.close()
