@@ -1,20 +1,27 @@
 """Benchmark of the lattice sweep on one MI355X.
 
-Default workload (the headline line): one 256^3 periodic box holding a carbon particle of
-radius 112 sites (pore-field correlation length 8 sites, widths 0.7-2.0 nm), uniform start,
-FID and MSD moments recorded every step, run once on the FP64 path and once on the mixed
-path (float storage, double sums). A step is one time step of the whole sweep: hop
-probabilities, population, magnetisation and moment updates, boundary handling and the
-per-step FP64 sums; the spectrum, its peak and the diffusion coefficients are computed on
-the device once at the end of the timed run. Inputs are resident in HBM before timing.
+Default workload (the headline line, `--workload film`): the supercapacitor film, a
+2048 x 256 x 256 lattice (134 M sites) closed in x and periodic in y and z, with two
+768-site porous electrodes (lognormal pore widths, median 0.9 and 1.3 nm, correlation
+length 6, biases +-0.5 kT) around a 512-site bulk electrolyte; Boltzmann start, FID per
+region and MSD moments recorded every step, on the mixed path (float storage, double
+populations and sums). The same line carries the 256^3 single particle (radius 112,
+correlation length 8) on the FP64 and the mixed path under `particle_256`.
 
-Other workloads (--workload): `batch` (512 particles of radius 8-48 in one batched sweep,
-against the same particles run one at a time), `film` (2048 x 256 x 256 supercapacitor
-film, closed in x), `serve` (Poisson arrivals of spectrum requests through the
-continuous-batching server), `equilibrate` (the population-only equilibration phase on the
-256^3 particle), `porous` (the same particle with a solid matrix, link mobility and
-reservoir faces), `supercap` (the monolith / film supercapacitor study at two potentials)
-and `copy` (plain device copy). Each prints one JSON line.
+A step is one time step of the whole sweep: hop probabilities, population, magnetisation
+and moment updates, boundary handling and the per-step FP64 sums (the sweep launches and
+their record finalisation, i.e. `lpc_run`). The timed region holds `lpc_run` alone, with
+inputs resident in HBM; the spectrum, its peak and the diffusion coefficients are computed
+on the device afterwards, their kernels warmed before, and timed on their own
+(`post_ms`).
+
+Other workloads (--workload): `particle` (the 256^3 particle alone), `batch` (512
+particles of radius 8-48 in one batched sweep, against the same particles run one at a
+time), `serve` (Poisson arrivals of spectrum requests through the continuous-batching
+server), `equilibrate` (the population-only equilibration phase on the 256^3 particle),
+`porous` (the same particle with a solid matrix, link mobility and reservoir faces),
+`supercap` (the monolith / film supercapacitor study at two potentials) and `copy` (plain
+device copy). Each prints one JSON line.
 """
 from __future__ import annotations
 
@@ -32,25 +39,41 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 SWEEP_SRC = os.path.join(ROOT, "paper_2603_22553_amd", "csrc", "sweep.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_256cubed_hbm_traffic.md")
+PROFILES = os.path.join(ROOT, "profiles")
 METRIC = "Glattice-site-updates/s (GSU/s) and fraction of HBM roofline"
 
 
-def bytes_per_site_update(precision: str, track=("fid", "msd"), n_regions: int = 2) -> int:
-    """Algorithmic HBM bytes of one site-update with one step per pass: the state read once
-    and written once, the fields read once."""
+def bytes_per_site_update(precision: str, track=("fid", "msd"), mobility: bool = False) -> int:
+    """Algorithmic HBM bytes of one site-update at one step per pass: the state read once and
+    written once, the fields read once. Per site the state is the population (double on both
+    paths), the magnetisation (2 values) and the moments (6 values) in the storage type; the
+    fields are the free energy, the per-step rotation (cos t - 1, sin t: 2 values), the region
+    byte and, with link mobility, the mobility (storage type). FP64 full 169 B, mixed full 93 B,
+    mixed FID-only 45 B, FP64 FID-only 73 B, FP64 populations-only 25 B."""
     s = 8 if precision == "fp64" else 4
-    state = 8                      # rho, always double
+    state = 8
+    fields = s + 1
     if "fid" in track:
-        state += 2 * s             # Re m, Im m
+        state += 2 * s
+        fields += 2 * s
     if "msd" in track:
-        state += 6 * s             # M1, M2 per axis
-    fields = s                     # F
-    if "fid" in track:
-        fields += s                # phase per step
-    if n_regions > 1:
-        fields += 1                # region id
+        state += 6 * s
+    if mobility:
+        fields += s
     return 2 * state + fields
+
+
+def built_bytes_per_site_update(precision: str, track=("fid", "msd"), n_regions: int = 2,
+                                mobility: bool = False) -> int:
+    """Bytes the kernel itself streams per site-update: it stores the phase t (one value)
+    instead of the rotation pair, and reads the region byte only with more than one region."""
+    s = 8 if precision == "fp64" else 4
+    b = bytes_per_site_update(precision, track, mobility)
+    if "fid" in track:
+        b -= s
+    if n_regions == 1:
+        b -= 1
+    return b
 
 
 def sweep_source_hash() -> str:
@@ -58,28 +81,32 @@ def sweep_source_hash() -> str:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def measured_traffic(precision: str):
-    """HBM bytes per sweep launch from the committed rocprofv3 counter summary, if it was
-    taken on the current kernel source; otherwise None."""
-    if not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(summary: str, key: str):
+    """HBM bytes per sweep launch (FETCH_SIZE + WRITE_SIZE, scaled by the copy calibration)
+    from a committed rocprofv3 counter summary under profiles/, if it was taken on the
+    current kernel source; otherwise None."""
+    path = os.path.join(PROFILES, summary)
+    if not os.path.exists(path):
         return None
-    text = open(TRAFFIC_FILE).read()
+    text = open(path).read()
     m = re.search(r"kernel source sha256\[:16\]:\s*([0-9a-f]{16})", text)
     if not m or m.group(1) != sweep_source_hash():
         return None
-    m = re.search(rf"{precision} bytes per launch:\s*([0-9.eE+]+)", text)
+    m = re.search(rf"{re.escape(key)} bytes per launch:\s*([0-9.eE+]+)", text)
     return float(m.group(1)) if m else None
 
 
-def roofline(n_sites, precision, ms_step, track=("fid", "msd"), n_regions=2, measured=False):
-    """Roofline object of one sweep launch; `traffic` is the counter reading of the 256^3
-    particle workload (measured=True there only; other workloads have not been counted)."""
-    b = bytes_per_site_update(precision, track, n_regions)
+def roofline(n_sites, precision, ms_step, track=("fid", "msd"), traffic=None, mobility=False,
+             n_regions=2):
+    """Roofline object of one sweep launch (one step of n_sites sites): algorithmic bytes
+    per launch over the measured time per launch, against the 8 TB/s HBM peak."""
+    b = bytes_per_site_update(precision, track, mobility)
     ach = n_sites * b / (ms_step * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(precision) if measured else None,
-            "bytes_per_site_update": b}
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "bytes_per_site_update": b,
+            "kernel_bytes_per_site_update": built_bytes_per_site_update(precision, track,
+                                                                        n_regions, mobility)}
 
 
 def timed(stream, fn):
@@ -96,6 +123,34 @@ def timed(stream, fn):
     return out, t0.elapsed_time(t1)
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def run_timed(lat, steps, warmup, regions=(None,), msd=True):
+    """Warm-up steps, one warm pass of the post-processing kernels, then `steps` steps
+    timed alone (lpc_run: sweeps and record finalisation) and the post-processing timed on
+    its own."""
+    lat.run(warmup)
+
+    def post():
+        peaks = [lat.peak_ppm(r) for r in regions]
+        return peaks, (lat.diffusion() if msd else (None, None))
+
+    post()
+    lat.synchronize()
+    _, ms = timed(lat.stream, lambda: lat.run(steps))
+    (peaks, (D, ratio)), ms_post = timed(lat.stream, post)
+    return ms, ms_post, peaks, D, ratio
+
+
 # ------------------------------------------------------------------- single large particle
 
 def run_particle(f, precision, steps, warmup, track=("fid", "msd")):
@@ -104,37 +159,66 @@ def run_particle(f, precision, steps, warmup, track=("fid", "msd")):
                   max_records=steps + warmup + 1)
     lat.set_fields(f)
     lat.init_state("uniform")
-    lat.run(warmup)
-    lat.synchronize()
-
     msd = "msd" in track
-
-    def work():
-        lat.run(steps)
-        return lat.peak_ppm(), (lat.diffusion() if msd else (None, None))
-
-    (peak, (D, ratio)), ms = timed(lat.stream, work)
+    ms, ms_post, peaks, D, ratio = run_timed(lat, steps, warmup, msd=msd)
     lat.check()                    # finite FID, population conserved to 1e-12
     mass = lat.moments()[0]
-    out = {"ms": ms, "gsu_s": f.n_sites * steps / (ms * 1e-3) / 1e9,
-           "mass_drift": float(abs(mass[-1] / mass[0] - 1.0)), "peak_ppm": peak,
+    out = {"ms": ms, "post_ms": ms_post, "gsu_s": f.n_sites * steps / (ms * 1e-3) / 1e9,
+           "mass_drift": float(abs(mass[-1] / mass[0] - 1.0)), "peak_ppm": peaks[0],
            "D_over_Dbulk": [round(float(v), 6) for v in ratio] if msd else None, "D": D,
            "plan": lat.describe(), "fid": lat.fid(), "uptake": lat.uptake()[-1]}
     lat.close()
     return out
 
 
-def cpu_baseline(f, steps, moments=True):
+def cpu_baseline(f, steps, moments=True, what="", **kw):
+    """The FP64 oracle (plain C, OpenMP) timed on the host cores over `steps` steps of the
+    same lattice."""
     from oracle import oracle
     oracle.build(force=False)
     t = time.perf_counter()
-    oracle.run(f.F, f.delta, f.region, f.n_regions, steps, moments=moments)
+    oracle.run(f.F, f.delta, f.region, f.n_regions, steps, moments=moments, **kw)
     dt = time.perf_counter() - t
-    what = "FID + MSD" if moments else "FID only"
+    tracked = "FID + MSD" if moments else "FID only"
     return {"value": round(f.n_sites * steps / dt / 1e9, 5), "unit": "GSU/s",
-            "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"{steps} steps of the same 256^3 particle lattice (FP64, {what}, "
-                      f"{f.n_sites * steps:.3g} site-updates), {dt:.1f} s"}
+            "cores": oracle.threads(), "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": f"{steps} steps of {what} (FP64, {tracked}, "
+                      f"{f.n_sites * steps:.3g} site-updates), {dt:.1f} s including set-up"}
+
+
+def particle_lines(f, args, precisions, track):
+    """Per-precision results and roofline entries of the 256^3 particle."""
+    full = track == ("fid", "msd")
+    res, lines = {}, {}
+    for p in precisions:
+        r = run_particle(f, p, args.steps_particle, args.warmup, track)
+        res[p] = r
+        ms_p = r["ms"] / args.steps_particle
+        print(f"# particle {p}: {r['gsu_s']:.2f} GSU/s, {ms_p:.4f} ms/step, {r['plan']}",
+              file=sys.stderr, flush=True)
+        lines[p] = {"value": round(r["gsu_s"], 4), "unit": "GSU/s", "steps": args.steps_particle,
+                    "ms_per_step": round(ms_p, 6), "post_ms": round(r["post_ms"], 3),
+                    "dtype": "f64" if p == "fp64" else "f32-storage/f64-sums",
+                    "roofline": roofline(f.n_sites, p, ms_p, track=track,
+                                         traffic=measured_traffic(
+                                             "sweep_particle_256cubed_hbm_traffic.md", p)
+                                         if full else None),
+                    "plan": r["plan"],
+                    "results": {"mass_drift": r["mass_drift"], "peak_ppm": round(r["peak_ppm"], 5),
+                                "D_over_Dbulk": r["D_over_Dbulk"]}}
+    if "fp64" in res and "mixed" in res:
+        # the FP32-storage path against the FP64 path over the whole run (the FP64 path itself
+        # is held to the oracle at 1e-10 by the parity tests)
+        import numpy as np
+        a, m = res["fp64"], res["mixed"]
+        lines["precision_comparison"] = {
+            "fid_rel_l2": float(np.linalg.norm(m["fid"] - a["fid"]) / np.linalg.norm(a["fid"])),
+            "uptake_max_rel": float(np.max(np.abs(m["uptake"] - a["uptake"]) / np.abs(a["uptake"]))),
+            "peak_ppm_diff": float(abs(m["peak_ppm"] - a["peak_ppm"])),
+            "D_max_rel": (float(np.max(np.abs(np.asarray(m["D"]) - a["D"]) / np.abs(a["D"])))
+                          if full else None),
+            "steps": args.steps_particle + args.warmup}
+    return lines
 
 
 def workload_particle(args):
@@ -143,68 +227,38 @@ def workload_particle(args):
     precisions = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
     track = tuple(args.track.split("+"))
     full = track == ("fid", "msd")
-    res = {}
-    for p in precisions:
-        res[p] = run_particle(f, p, args.steps, args.warmup, track)
-        print(f"# {p}: {res[p]['gsu_s']:.2f} GSU/s, {res[p]['ms'] / args.steps:.4f} ms/step, "
-              f"{res[p]['plan']}", file=sys.stderr, flush=True)
-    head = "fp64" if "fp64" in res else precisions[0]
-    r = res[head]
-    ms_step = r["ms"] / args.steps
+    args.steps_particle = args.steps
+    lines = particle_lines(f, args, precisions, track)
+    head = precisions[0]
+    h = lines.pop(head)
     line = {
-        "metric": METRIC, "value": round(r["gsu_s"], 4), "unit": "GSU/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 6),
+        "metric": METRIC, "value": h["value"], "unit": "GSU/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": h["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if head == "fp64" else "f32-storage/f64-sums", "data": "synthetic",
+        "dtype": h["dtype"], "data": "synthetic",
         "config": {"workload": "single large particle: 256^3 periodic box, radius-112 carbon "
                                "particle, " + ("FID + MSD" if full else "FID only")
-                               + " recorded every step",
+                               + " recorded every step, uniform start",
                    "sites": f.n_sites, "regions": f.n_regions, "precision": head,
-                   "steps_per_pass": 1, "plan": r["plan"]},
-        "roofline": roofline(f.n_sites, head, ms_step, track=track, measured=full),
-        "results": {"mass_drift": r["mass_drift"], "peak_ppm": round(r["peak_ppm"], 5),
-                    "D_over_Dbulk": r["D_over_Dbulk"]},
+                   "steps_per_pass": 1, "plan": h["plan"]},
+        "roofline": h["roofline"], "post_ms": h["post_ms"], "results": h["results"],
     }
-    for p, rr in res.items():
-        if p == head:
-            continue
-        ms_p = rr["ms"] / args.steps
-        line[p] = {"value": round(rr["gsu_s"], 4), "unit": "GSU/s", "ms_per_step": round(ms_p, 6),
-                   "dtype": "f32-storage/f64-sums",
-                   "roofline": roofline(f.n_sites, p, ms_p, track=track, measured=full),
-                   "results": {"mass_drift": rr["mass_drift"], "peak_ppm": round(rr["peak_ppm"], 5),
-                               "D_over_Dbulk": rr["D_over_Dbulk"]}}
-    if "fp64" in res and "mixed" in res:
-        # the FP32-storage path against the FP64 path over the whole run (the FP64 path itself
-        # is held to the oracle at 1e-10 by the parity tests)
-        import numpy as np
-        a, m = res["fp64"], res["mixed"]
-        line["precision_comparison"] = {
-            "fid_rel_l2": float(np.linalg.norm(m["fid"] - a["fid"]) / np.linalg.norm(a["fid"])),
-            "uptake_max_rel": float(np.max(np.abs(m["uptake"] - a["uptake"]) / np.abs(a["uptake"]))),
-            "peak_ppm_diff": float(abs(m["peak_ppm"] - a["peak_ppm"])),
-            "D_max_rel": (float(np.max(np.abs(np.asarray(m["D"]) - a["D"]) / np.abs(a["D"])))
-                          if full else None),
-            "steps": args.steps + args.warmup}
+    line.update(lines)
     if args.calibrate and full:
-        # achievable ceilings measured in the same run: a plain copy, and the sweep's own
-        # column pattern without its halo and arithmetic (FP64 full path)
-        cp, col, colm = copy_rate(10), columns_rate(10), columns_mixed_rate(10)
-        cal = {"copy_GBps": round(cp, 1), "sweep_pattern_GBps": round(col, 1),
-               "sweep_pattern_frac_of_peak": round(col / HBM_PEAK_GBS, 4),
-               "mixed_sweep_pattern_GBps": round(colm, 1)}
-        if "mixed" in line:
-            cal["mixed_algorithmic_frac_of_pattern"] = round(
-                line["mixed"]["roofline"]["achieved"] / colm, 4)
-        if head == "fp64":
-            cal["algorithmic_frac_of_pattern"] = round(line["roofline"]["achieved"] / col, 4)
-            tr = line["roofline"]["traffic"]
-            if tr:
-                cal["counter_traffic_frac_of_pattern"] = round(tr / (ms_step * 1e-3) / 1e9 / col, 4)
-        line["calibration"] = cal
+        line["calibration"] = calibration()
     if args.cpu_steps > 0:
-        line["cpu_baseline"] = cpu_baseline(f, args.cpu_steps, moments=full)
+        line["cpu_baseline"] = cpu_baseline(f, args.cpu_steps, moments=full,
+                                            what="the same 256^3 particle lattice")
     return line
+
+
+def calibration():
+    """Achievable ceilings measured in the same run: a plain copy, and each path's sweep
+    column pattern without its halo and arithmetic (256^3)."""
+    cp, col, colm = copy_rate(10), columns_rate(10), columns_mixed_rate(10)
+    return {"copy_GBps": round(cp, 1), "fp64_sweep_pattern_GBps": round(col, 1),
+            "mixed_sweep_pattern_GBps": round(colm, 1),
+            "copy_frac_of_peak": round(cp / HBM_PEAK_GBS, 4)}
 
 
 # ------------------------------------------------------------------- batched particles
@@ -275,44 +329,68 @@ def workload_batch(args):
 # ------------------------------------------------------------------- film
 
 def workload_film(args):
+    """The headline line: the 2048 x 256 x 256 supercapacitor film on the mixed path, with
+    the 256^3 particle (FP64 and mixed) beside it."""
     from paper_2603_22553_amd import synth
     from paper_2603_22553_amd.lattice import Lattice
     t = time.perf_counter()
     f = synth.film()
     print(f"# generated film in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
     steps = args.steps
-    lat = Lattice(f.shape_xyz, bc=("closed", "periodic", "periodic"), precision="mixed",
-                  n_regions=3, max_records=steps + args.warmup + 1)
+    bc = ("closed", "periodic", "periodic")
+    lat = Lattice(f.shape_xyz, bc=bc, precision="mixed", n_regions=3,
+                  max_records=steps + args.warmup + 1)
     lat.set_fields(f)
     lat.init_state("boltzmann")
-    lat.run(args.warmup)
-
-    def work():
-        lat.run(steps)
-        return [lat.peak_ppm(r) for r in range(3)], lat.diffusion()
-
-    (peaks, (D, ratio)), ms = timed(lat.stream, work)
+    ms, ms_post, peaks, D, ratio = run_timed(lat, steps, args.warmup, regions=(0, 1, 2))
     lat.check()
     prof = lat.uptake_profile(0)
     plan = lat.describe()
+    mass = lat.moments()[0]
     lat.close()
+    del lat
     ms_step = ms / steps
-    return {
+    print(f"# film mixed: {f.n_sites * steps / (ms * 1e-3) / 1e9:.2f} GSU/s, {ms_step:.4f} ms/step, "
+          f"{plan}", file=sys.stderr, flush=True)
+    line = {
         "metric": METRIC, "value": round(f.n_sites * steps / (ms * 1e-3) / 1e9, 4),
         "unit": "GSU/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 6), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32-storage/f64-sums", "data": "synthetic",
-        "config": {"workload": "supercapacitor film 2048x256x256, electrodes 768 | bulk 512 | "
-                               "768 sites, closed in x, Boltzmann start, FID + MSD",
-                   "sites": f.n_sites, "plan": plan},
-        "roofline": roofline(f.n_sites, "mixed", ms_step, n_regions=3),
+        "config": {"workload": "supercapacitor film 2048x256x256: electrodes 768 | bulk 512 | "
+                               "768 sites, closed in x, periodic in y and z, Boltzmann start, "
+                               "FID per region + MSD recorded every step",
+                   "sites": f.n_sites, "regions": 3, "precision": "mixed",
+                   "steps_per_pass": 1, "plan": plan},
+        "roofline": roofline(f.n_sites, "mixed", ms_step, n_regions=3,
+                             traffic=measured_traffic("sweep_film_2048x256x256_hbm_traffic.md",
+                                                      "mixed")),
+        "post_ms": round(ms_post, 3),
         "results": {"peak_ppm_bulk_A_B": [round(p, 4) for p in peaks],
                     "D_over_Dbulk": [round(float(v), 5) for v in ratio],
+                    "mass_drift": float(abs(mass[-1] / mass[0] - 1.0)),
                     "uptake_per_site_A_bulk_B": [
                         round(float(prof[:768].mean() / (256 * 256)), 5),
                         round(float(prof[768:1280].mean() / (256 * 256)), 5),
                         round(float(prof[1280:].mean() / (256 * 256)), 5)]},
     }
+    if args.cpu_steps > 0:
+        from oracle import oracle
+        line["cpu_baseline"] = cpu_baseline(f, args.cpu_steps, what="the same film lattice",
+                                            bc=(oracle.CLOSED, oracle.PERIODIC, oracle.PERIODIC),
+                                            init="boltzmann")
+    del f
+    if args.particle_steps > 0:
+        psynth = synth.single_particle_large()
+        args.steps_particle = args.particle_steps
+        line["particle_256"] = {
+            "workload": "256^3 periodic box, radius-112 carbon particle, FID + MSD, uniform start",
+            "sites": psynth.n_sites}
+        line["particle_256"].update(particle_lines(psynth, args, ["fp64", "mixed"],
+                                                   ("fid", "msd")))
+    if args.calibrate:
+        line["calibration"] = calibration()
+    return line
 
 
 # ------------------------------------------------------------------- porous particle, reservoirs
@@ -335,14 +413,8 @@ def workload_porous(args):
         for side in (0, 1):
             lat.set_reservoir(0, side, 0.0, 1.0, 1.0)
         lat.init_state("boltzmann")
-        lat.run(args.warmup)
-        lat.synchronize()
-
-        def work():
-            lat.run(args.steps)
-            return lat.peak_ppm(), lat.diffusion()
-
-        (peak, (D, ratio)), ms = timed(lat.stream, work)
+        ms, _, peaks, D, ratio = run_timed(lat, args.steps, args.warmup)
+        peak = peaks[0]
         mass = lat.moments()[0]
         plan = lat.describe()
         lat.close()
@@ -354,10 +426,7 @@ def workload_porous(args):
     for p, r in res.items():
         ms_step = r["ms"] / args.steps
         # the mobility field is one more field read per site-update
-        b = bytes_per_site_update(p, ("fid", "msd"), f.n_regions) + (8 if p == "fp64" else 4)
-        ach = f.n_sites * b / (ms_step * 1e-3) / 1e9
-        rl = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-              "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_site_update": b}
+        rl = roofline(f.n_sites, p, ms_step, mobility=True, n_regions=f.n_regions)
         entry = {"value": round(r["gsu_s"], 4), "unit": "GSU/s", "ms_per_step": round(ms_step, 6),
                  "dtype": "f64" if p == "fp64" else "f32-storage/f64-sums", "roofline": rl,
                  "results": {"peak_ppm": round(r["peak"], 4), "D_over_Dbulk": r["ratio"],
@@ -634,17 +703,20 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", choices=["particle", "batch", "film", "serve", "copy",
+    ap.add_argument("--workload", choices=["film", "particle", "batch", "serve", "copy",
                                            "equilibrate", "porous", "supercap"],
-                    default="particle")
+                    default="film")
     ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both")
     ap.add_argument("--track", choices=["fid+msd", "fid"], default="fid+msd",
                     help="particle workload: recorded quantities (fid: the serving kernel)")
     ap.add_argument("--calibrate", type=int, default=1,
-                    help="particle workload: also time a plain copy and the sweep's column "
-                         "pattern (achievable ceilings) and report them beside the roofline")
-    ap.add_argument("--cpu-steps", type=int, default=20,
-                    help="oracle steps timed for the CPU baseline (0 skips it)")
+                    help="film and particle workloads: also time a plain copy and the sweeps' "
+                         "column patterns (achievable ceilings) and report them")
+    ap.add_argument("--cpu-steps", type=int, default=None,
+                    help="oracle steps timed for the CPU baseline (0 skips it; default 12 on "
+                         "the film, 20 on the particle)")
+    ap.add_argument("--particle-steps", type=int, default=2000,
+                    help="film workload: steps of the 256^3 particle timed beside it (0 skips)")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-rate", type=float, default=20.0)
@@ -660,13 +732,15 @@ def main():
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the sweep "
               "would shard by slabs with one halo exchange per pass; not built).", file=sys.stderr)
         sys.exit(2)
-    defaults = {"particle": (50000, 200), "batch": (2000, 20), "film": (1000, 20),
+    defaults = {"particle": (50000, 200), "batch": (2000, 20), "film": (2000, 20),
                 "serve": (0, 0), "copy": (20, 1), "equilibrate": (5000, 200),
                 "porous": (5000, 100), "supercap": (50000, 0)}[args.workload]
     if args.steps is None:
         args.steps = defaults[0]
     if args.warmup is None:
         args.warmup = defaults[1]
+    if args.cpu_steps is None:
+        args.cpu_steps = {"film": 12, "particle": 20}.get(args.workload, 0)
 
     import torch
     assert torch.cuda.is_available(), "no GPU"

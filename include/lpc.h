@@ -219,6 +219,34 @@ lpc_status lpc_diffusion(lpc_lattice *lat, double *D_m2_s, double *ratio);
  * units^2); needs LPC_TRACK_MSD and N >= 2. */
 lpc_status lpc_read_vacf(lpc_lattice *lat, double *vacf_xyz, int64_t cap, int64_t *len);
 
+/* Kohn estimate of the diffusion coefficient, Eq. (4) (section 2.2): the discrete velocity
+ * autocorrelation of lpc_read_vacf summed up to lag T, D_a(T) = a^2 [C_a(0)/2 +
+ * sum_{tau=1}^{T} C_a(tau)] / dt_s per axis, in m^2/s (3 values). lag = -1 takes every
+ * recorded lag (T = N - 1); otherwise 0 <= lag <= N - 1. Valid for runs started from
+ * equilibrium, as lpc_read_vacf. Needs LPC_TRACK_MSD and N >= 2. */
+lpc_status lpc_kohn_diffusion(lpc_lattice *lat, int64_t lag, double *D_m2_s);
+
+/* Attempt probability per neighbour for a mean residence time tau_s on a free site (the
+ * residence times of section 4): a particle on a site with six accessible neighbours of
+ * equal free energy leaves with probability 6 p_hop per step, so its stay is geometric with
+ * mean dt_s / (6 p_hop), and p_hop = dt_s / (6 tau_s). Host-only. LPC_ERR_ARG unless
+ * tau_s >= dt_s > 0 (both finite), or for a NULL p_hop. */
+lpc_status lpc_p_hop_from_residence_time(double tau_s, double dt_s, double *p_hop);
+
+/* Per-part diffusion coefficients (section 4, Table 1) from two tables of lpc_region_moments
+ * taken steps_between >= 1 steps apart (sums_a first, sums_b later; 7 values per region, as
+ * lpc_region_moments writes them). For region r the mean-square displacement of the
+ * particles now in it is MSD_r,a = sum M2_a / sum rho over its sites; its slope per step,
+ * averaged over the axes whose bit is set in `axes` (bit a for axis a, 1..7), gives
+ * D_r = spacing_m^2 slope / (2 dt_s) in m^2/s and ratio_r = slope / (2 p_hop), the
+ * free-lattice value being 1 (Eq. (7)). Writes n_regions values to each of D_m2_s and
+ * ratio. Host-only. LPC_ERR_ARG for NULL arrays, n_regions outside 1..LPC_MAX_REGIONS,
+ * steps_between < 1, axes outside 1..7, or p_hop, dt_s, spacing_m not positive and finite;
+ * LPC_ERR_STATE if a region holds no population in either table. */
+lpc_status lpc_region_diffusion(const double *sums_a, const double *sums_b, int32_t n_regions,
+                                int64_t steps_between, double p_hop, double dt_s,
+                                double spacing_m, uint32_t axes, double *D_m2_s, double *ratio);
+
 /* Per-region sums over the current state, 7 per region r < n_regions: the population and
  * the first and second displacement moments along x, y, z (moment propagation, section
  * 2.2): sums[7 r + q], q = 0 rho, 1..3 M1_x..z, 4..6 M2_x..z. M2 / rho of a region is the

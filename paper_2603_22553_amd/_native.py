@@ -97,6 +97,11 @@ SIGNATURES = {
     "lpc_equilibrate": [_P, _I64, ctypes.c_double, _I64, _PI64, ctypes.POINTER(ctypes.c_double)],
     "lpc_read_vacf": [_P, _P, _I64, _PI64],
     "lpc_region_moments": [_P, _P, _I64],
+    "lpc_kohn_diffusion": [_P, _I64, _P],
+    "lpc_p_hop_from_residence_time": [ctypes.c_double, ctypes.c_double,
+                                      ctypes.POINTER(ctypes.c_double)],
+    "lpc_region_diffusion": [_P, _P, _I32, _I64, ctypes.c_double, ctypes.c_double,
+                             ctypes.c_double, ctypes.c_uint32, _P, _P],
     "lpc_batch_query_footprint": [_I32, _PSZ],
     "lpc_batch_create": [_P, _I32, _P, _SZ, _P, ctypes.POINTER(_P)],
     "lpc_batch_destroy": [_P],

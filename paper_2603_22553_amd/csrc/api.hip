@@ -1297,6 +1297,28 @@ lpc_status lpc_read_vacf(lpc_lattice *lat, double *vacf_xyz, int64_t cap, int64_
     return ok();
 }
 
+lpc_status lpc_kohn_diffusion(lpc_lattice *lat, int64_t lag, double *D_m2_s)
+{
+    if (!lat || !D_m2_s)
+        return fail(LPC_ERR_ARG, "NULL argument");
+    const int64_t N = lat->steps_done;
+    if (N >= 2 && (lag < -1 || lag > N - 1))
+        return fail(LPC_ERR_ARG, "lag %lld outside -1..%lld", (long long)lag, (long long)(N - 1));
+    std::vector<double> C(size_t(std::max<int64_t>(N, 1)) * 3);
+    int64_t len = 0;
+    if (lpc_status s = lpc_read_vacf(lat, C.data(), N, &len))
+        return s;
+    const int64_t T = lag < 0 ? len - 1 : lag;
+    const double scale = lat->cfg.spacing_m * lat->cfg.spacing_m / lat->cfg.dt_s;
+    for (int a = 0; a < 3; ++a) {
+        double sum = 0.5 * C[size_t(a)];
+        for (int64_t tau = 1; tau <= T; ++tau)
+            sum += C[size_t(3 * tau + a)];
+        D_m2_s[a] = scale * sum;
+    }
+    return ok();
+}
+
 lpc_status lpc_region_moments(lpc_lattice *lat, double *sums, int64_t cap)
 {
     if (!lat || !sums)
@@ -1722,6 +1744,55 @@ lpc_status lpc_describe(const lpc_lattice *lat, char *buf, size_t cap)
              "arena %zu bytes",
              p.tx, p.ty, p.zc, p.gx, p.gy, p.gz, (long long)p.nblocks, (long long)lat->L.chunk,
              lat->L.total);
+    return ok();
+}
+
+lpc_status lpc_p_hop_from_residence_time(double tau_s, double dt_s, double *p_hop)
+{
+    if (!p_hop)
+        return fail(LPC_ERR_ARG, "p_hop is NULL");
+    if (!std::isfinite(tau_s) || !std::isfinite(dt_s) || !(dt_s > 0.0) || !(tau_s >= dt_s))
+        return fail(LPC_ERR_ARG, "need finite tau_s >= dt_s > 0 (tau_s = %g, dt_s = %g)", tau_s,
+                    dt_s);
+    // a free site is left with probability 6 p_hop per step: mean stay dt / (6 p_hop)
+    *p_hop = dt_s / (6.0 * tau_s);
+    return ok();
+}
+
+lpc_status lpc_region_diffusion(const double *sums_a, const double *sums_b, int32_t n_regions,
+                                int64_t steps_between, double p_hop, double dt_s,
+                                double spacing_m, uint32_t axes, double *D_m2_s, double *ratio)
+{
+    if (!sums_a || !sums_b || !D_m2_s || !ratio)
+        return fail(LPC_ERR_ARG, "NULL argument");
+    if (n_regions < 1 || n_regions > LPC_MAX_REGIONS)
+        return fail(LPC_ERR_ARG, "n_regions = %d outside 1..%d", n_regions, LPC_MAX_REGIONS);
+    if (steps_between < 1)
+        return fail(LPC_ERR_ARG, "steps_between must be >= 1");
+    if (axes < 1 || axes > 7)
+        return fail(LPC_ERR_ARG, "axes mask 0x%x: need bits of axes 0..2, at least one", axes);
+    for (double v : {p_hop, dt_s, spacing_m})
+        if (!std::isfinite(v) || !(v > 0.0))
+            return fail(LPC_ERR_ARG, "p_hop, dt_s and spacing_m must be positive and finite");
+    for (int32_t r = 0; r < n_regions; ++r)
+        if (!(sums_a[7 * r] != 0.0) || !(sums_b[7 * r] != 0.0))
+            return fail(LPC_ERR_STATE, "region %d holds no population", r);
+    int n_axes = 0;
+    for (int a = 0; a < 3; ++a)
+        n_axes += (axes >> a) & 1u;
+    for (int32_t r = 0; r < n_regions; ++r) {
+        const double *A = sums_a + 7 * r, *B = sums_b + 7 * r;
+        double slope = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            if (!((axes >> a) & 1u))
+                continue;
+            // mean-square displacement of the particles now in the region, per step
+            slope += (B[4 + a] / B[0] - A[4 + a] / A[0]) / double(steps_between);
+        }
+        slope /= n_axes;
+        D_m2_s[r] = spacing_m * spacing_m * slope / (2.0 * dt_s);
+        ratio[r] = slope / (2.0 * p_hop);
+    }
     return ok();
 }
 

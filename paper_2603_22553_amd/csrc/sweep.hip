@@ -45,6 +45,16 @@
 
 #include <algorithm>
 
+// The sweep's kernel instances are compiled in parts, one translation unit each, so that
+// the build runs them in parallel: LPC_SWEEP_PART 0 and 1 hold the FP64 instances (plain,
+// extended), 2 and 3 the float ones, and 4 the planning, the dispatch and every other
+// kernel. Without the macro one unit holds everything.
+#ifndef LPC_SWEEP_PART
+#define LPC_SWEEP_PART -1
+#endif
+#define LPC_PART_IS(k) (LPC_SWEEP_PART < 0 || LPC_SWEEP_PART == (k))
+#define LPC_HOST_PART LPC_PART_IS(4)
+
 namespace lpc {
 namespace {
 
@@ -964,6 +974,7 @@ __global__ __launch_bounds__(kThreads) void k_record_tile(StepArgs a, SweepPlan 
     block_reduce<MAXR, kThreads / kWave>(acc, a.R, a.K, a.partials, p.nblocks, blk, red);
 }
 
+#if LPC_HOST_PART
 // Sum of one record entry over the workgroup partials p[0, nblocks), in a fixed order.
 __device__ inline double partial_sum(const double *p, int64_t nblocks, double *w)
 {
@@ -1147,6 +1158,8 @@ int grid_for(int64_t n, int threads)
     return static_cast<int>(g < 1 ? 1 : g);
 }
 
+#endif  // LPC_HOST_PART
+
 // ---------------------------------------------------------------------------- dispatch
 
 struct RecordLauncher {
@@ -1211,23 +1224,76 @@ hipError_t by_fields(const SweepPlan &p, const StepArgs &a, hipStream_t s, X... 
     return by_regions<L, S, false, false, EXT>(p, a, s, x...);
 }
 
-template <typename L, typename S, typename... X>
-hipError_t by_track(const SweepPlan &p, const StepArgs &a, hipStream_t s, X... x)
-{
-    if (a.track & kVariantExtended)
-        return by_fields<L, S, true>(p, a, s, x...);
-    return by_fields<L, S, false>(p, a, s, x...);
-}
-
-template <typename L, typename... X>
-hipError_t by_precision(const SweepPlan &p, const StepArgs &a, hipStream_t s, X... x)
-{
-    if (a.precision == 0)
-        return by_track<L, double>(p, a, s, x...);
-    return by_track<L, float>(p, a, s, x...);
-}
+struct OccupancyQuery {
+    template <typename S, bool FID, bool MSD, bool EXT, int MAXR>
+    static hipError_t go(const SweepPlan &, const StepArgs &, hipStream_t, int *out)
+    {
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            out, reinterpret_cast<const void *>(&k_sweep_tile<S, FID, MSD, EXT, MAXR, 64>),
+            kThreads, 0);
+    }
+};
 
 }  // namespace
+
+// Per-part entry points: the sweep work list, the occupancy query and the record kernel of
+// one storage type and variant (defined in the part that compiles those instances).
+template <typename S, bool EXT>
+hipError_t step_list_part(const StepList &L, uint32_t track, int32_t maxr, hipStream_t s);
+template <typename S, bool EXT>
+int occupancy_part(uint32_t track, int32_t R);
+template <typename S>
+hipError_t record_part(const SweepPlan &plan, const StepArgs &a, hipStream_t s);
+
+#if !(LPC_SWEEP_PART == 4)
+template <typename S, bool EXT>
+hipError_t step_list_part(const StepList &L, uint32_t track, int32_t maxr, hipStream_t s)
+{
+    StepArgs a{};
+    a.track = track;
+    a.R = maxr;
+    return by_fields<ListLauncher, S, EXT>(SweepPlan{}, a, s, &L);
+}
+
+template <typename S, bool EXT>
+int occupancy_part(uint32_t track, int32_t R)
+{
+    StepArgs a{};
+    a.track = track;
+    a.R = R;
+    int n = 0;
+    if (by_fields<OccupancyQuery, S, EXT>(SweepPlan{}, a, nullptr, &n) != hipSuccess || n < 1)
+        return 1;
+    return n;
+}
+
+template <typename S>
+hipError_t record_part(const SweepPlan &plan, const StepArgs &a, hipStream_t s)
+{
+    return by_fields<RecordLauncher, S, false>(plan, a, s);
+}
+#endif
+
+#if LPC_PART_IS(0)
+template hipError_t step_list_part<double, false>(const StepList &, uint32_t, int32_t, hipStream_t);
+template int occupancy_part<double, false>(uint32_t, int32_t);
+template hipError_t record_part<double>(const SweepPlan &, const StepArgs &, hipStream_t);
+#endif
+#if LPC_PART_IS(1)
+template hipError_t step_list_part<double, true>(const StepList &, uint32_t, int32_t, hipStream_t);
+template int occupancy_part<double, true>(uint32_t, int32_t);
+#endif
+#if LPC_PART_IS(2)
+template hipError_t step_list_part<float, false>(const StepList &, uint32_t, int32_t, hipStream_t);
+template int occupancy_part<float, false>(uint32_t, int32_t);
+template hipError_t record_part<float>(const SweepPlan &, const StepArgs &, hipStream_t);
+#endif
+#if LPC_PART_IS(3)
+template hipError_t step_list_part<float, true>(const StepList &, uint32_t, int32_t, hipStream_t);
+template int occupancy_part<float, true>(uint32_t, int32_t);
+#endif
+
+#if LPC_HOST_PART
 
 // Tile width for a lattice of nx columns: the widest tile whose padded width is within
 // 1.5 times the least padded width. Full 64-site rows load far better than narrow ones, more
@@ -1334,48 +1400,24 @@ SweepPlan with_z_chunk(SweepPlan p, const Geometry &g, int32_t zc)
     return p;
 }
 
-struct OccupancyQuery {
-    template <typename S, bool FID, bool MSD, bool EXT, int MAXR>
-    static hipError_t go(const SweepPlan &, const StepArgs &, hipStream_t, int *out)
-    {
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            out, reinterpret_cast<const void *>(&k_sweep_tile<S, FID, MSD, EXT, MAXR, 64>),
-            kThreads, 0);
-    }
-};
-
-struct LinearLimit {
-    template <typename S, bool FID, bool MSD, bool EXT, int>
-    static hipError_t go(const SweepPlan &, const StepArgs &, hipStream_t, int *out)
-    {
-        *out = EXT ? 0 : linear_nx_max<S, FID, MSD>();
-        return hipSuccess;
-    }
-};
-
 int32_t linear_tile_max_nx(int32_t precision, uint32_t track)
 {
-    StepArgs a{};
-    a.precision = precision;
-    a.track = track;
-    a.R = 1;
-    int n = 0;
-    if (by_precision<LinearLimit>(SweepPlan{}, a, nullptr, &n) != hipSuccess)
+    if (track & kVariantExtended)
         return 0;
-    return n;
+    const bool fid = track & 1u, msd = track & 2u;
+    if (precision == 0)
+        return fid ? (msd ? linear_nx_max<double, true, true>() : linear_nx_max<double, true, false>())
+                   : (msd ? linear_nx_max<double, false, true>() : linear_nx_max<double, false, false>());
+    return fid ? (msd ? linear_nx_max<float, true, true>() : linear_nx_max<float, true, false>())
+               : (msd ? linear_nx_max<float, false, true>() : linear_nx_max<float, false, false>());
 }
 
 int sweep_blocks_per_cu(int32_t precision, uint32_t track, int32_t R)
 {
-    StepArgs a{};
-    a.precision = precision;
-    a.track = track;
-    a.R = R;
-    SweepPlan p{};
-    int n = 0;
-    if (by_precision<OccupancyQuery>(p, a, nullptr, &n) != hipSuccess || n < 1)
-        return 1;
-    return n;
+    const bool ext = track & kVariantExtended;
+    if (precision == 0)
+        return ext ? occupancy_part<double, true>(track, R) : occupancy_part<double, false>(track, R);
+    return ext ? occupancy_part<float, true>(track, R) : occupancy_part<float, false>(track, R);
 }
 
 hipError_t launch_step_list(const StepList &L, int32_t precision, uint32_t track, int32_t maxr,
@@ -1383,16 +1425,17 @@ hipError_t launch_step_list(const StepList &L, int32_t precision, uint32_t track
 {
     if (L.total <= 0)
         return hipSuccess;
-    StepArgs a{};
-    a.precision = precision;
-    a.track = track;
-    a.R = maxr;
-    return by_precision<ListLauncher>(SweepPlan{}, a, s, &L);
+    const bool ext = track & kVariantExtended;
+    if (precision == 0)
+        return ext ? step_list_part<double, true>(L, track, maxr, s)
+                   : step_list_part<double, false>(L, track, maxr, s);
+    return ext ? step_list_part<float, true>(L, track, maxr, s)
+               : step_list_part<float, false>(L, track, maxr, s);
 }
 
 hipError_t launch_record(const SweepPlan &plan, const StepArgs &a, hipStream_t s)
 {
-    return by_precision<RecordLauncher>(plan, a, s);
+    return a.precision == 0 ? record_part<double>(plan, a, s) : record_part<float>(plan, a, s);
 }
 
 hipError_t launch_finalize_list(const FinalizeItem *items, const int64_t *kprefix, int32_t n_items,
@@ -1493,5 +1536,7 @@ hipError_t launch_boltzmann_scale(double *w, int64_t n, double numer, const doub
     hipLaunchKernelGGL(k_boltzmann_scale, dim3(grid_for(n, 256)), dim3(256), 0, s, w, n, numer, Z);
     return hipGetLastError();
 }
+
+#endif  // LPC_HOST_PART
 
 }  // namespace lpc

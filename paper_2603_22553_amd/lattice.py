@@ -23,13 +23,34 @@ def _ptr(a: np.ndarray):
 
 
 def p_hop_from_residence_time(tau_s: float, dt_s: float) -> float:
-    """Attempt probability per neighbour for a mean residence time tau on a free site:
-    a particle leaves with probability 6 p_hop per step, so tau = dt / (6 p_hop) (the
-    residence times of section 4, 1 ms and 0.2 ms at dt = 5 us, give p_hop = 1/1200 and
-    1/240)."""
-    if tau_s < dt_s:
-        raise ValueError("the residence time must be at least one time step")
-    return dt_s / (6.0 * tau_s)
+    """Attempt probability per neighbour for a mean residence time tau on a free site
+    (lpc_p_hop_from_residence_time); raises ValueError where the library rejects the
+    arguments."""
+    v = ctypes.c_double()
+    st = N.status("lpc_p_hop_from_residence_time", float(tau_s), float(dt_s), ctypes.byref(v))
+    if st != N.LPC_OK:
+        raise ValueError(N.load().lpc_last_error().decode())
+    return float(v.value)
+
+
+def region_diffusion(sums_a, sums_b, steps_between: int, p_hop: float, dt_s: float = 5e-6,
+                     spacing_m: float = 0.5e-9, axes=(0, 1, 2)):
+    """Per-region diffusion (lpc_region_diffusion) from two region-moment tables taken
+    steps_between steps apart, averaged over `axes`. Returns (D in m^2/s, D / D_bulk), one
+    value per region each."""
+    a = np.ascontiguousarray(sums_a, dtype=np.float64).reshape(-1)
+    b = np.ascontiguousarray(sums_b, dtype=np.float64).reshape(-1)
+    R = a.size // 7
+    if a.size != 7 * R or b.size != a.size:
+        raise ValueError("region tables must hold 7 values per region, both of one size")
+    D = np.empty(R)
+    ratio = np.empty(R)
+    mask = 0
+    for ax in axes:
+        mask |= 1 << int(ax)
+    N.call("lpc_region_diffusion", _ptr(a), _ptr(b), R, int(steps_between), float(p_hop),
+           float(dt_s), float(spacing_m), mask, _ptr(D), _ptr(ratio))
+    return D, ratio
 
 
 def make_config(shape_xyz, bc=("periodic",) * 3, precision="fp64", track=("fid", "msd"),
@@ -299,10 +320,9 @@ class Lattice:
 
     def kohn_diffusion(self, lag=None) -> np.ndarray:
         """Eq. (4) truncated at `lag` (default: all recorded lags), m^2/s per axis."""
-        C = self.vacf()
-        T = C.shape[0] - 1 if lag is None else int(lag)
-        a2 = self.cfg.spacing_m ** 2
-        return a2 * (0.5 * C[0] + C[1:T + 1].sum(axis=0)) / self.cfg.dt_s
+        D = np.empty(3)
+        N.call("lpc_kohn_diffusion", self.handle, -1 if lag is None else int(lag), _ptr(D))
+        return D
 
     def uptake_profile(self, axis=0) -> np.ndarray:
         n = self.shape_xyz[axis] if 0 <= axis < 3 else 1   # the library validates the axis

@@ -115,22 +115,13 @@ def system(kind: str = "monolith", potential_v: float = 0.0, shape_xyz=(100, 100
     return System(f, kind, potential_v, carbon)
 
 
-def part_diffusion(mom_a, mom_b, steps_between, p_hop):
-    """D / D_bulk per part, in the electrode plane (mean over x and y), from two region
-    moment tables (rows: parts; columns rho, M1 xyz, M2 xyz) taken `steps_between` apart."""
-    msd_a = mom_a[:, 4:7] / mom_a[:, :1]
-    msd_b = mom_b[:, 4:7] / mom_b[:, :1]
-    slope = (msd_b - msd_a) / steps_between          # lattice units^2 per step
-    return (slope[:, :2].mean(axis=1)) / (2.0 * p_hop)
-
-
 def run_batch(systems, steps: int = 50000, tau_s: float = 1e-3, dt_s: float = 5e-6,
               larmor_hz: float = 282e6, precision: str = "mixed", spacing_m: float = 0.5e-9):
     """Propagation runs of several supercapacitors on the GPU, stepped together as one
     batch (one launch per step covers every lattice, each ending bit for bit as if run
     alone); returns per-part results per system and the batch's propagation time."""
     import torch
-    from .lattice import Batch, Lattice, p_hop_from_residence_time
+    from .lattice import Batch, Lattice, p_hop_from_residence_time, region_diffusion
     p_hop = p_hop_from_residence_time(tau_s, dt_s)
     half = steps // 2
     lats = []
@@ -161,7 +152,9 @@ def run_batch(systems, steps: int = 50000, tau_s: float = 1e-3, dt_s: float = 5e
         for sysm, lat, up, ma, mb in zip(systems, lats, uptake, mom_a, mom_b):
             peaks = [lat.peak_ppm(r) for r in range(3)]
             lat.check()
-            ratio = part_diffusion(ma, mb, steps - half, p_hop)
+            # in the electrode plane (x, y); z is closed at the electrode backs
+            _, ratio = region_diffusion(ma, mb, steps - half, p_hop, dt_s, spacing_m,
+                                        axes=(0, 1))
             out.append({"kind": sysm.kind, "potential_v": sysm.potential_v, "tau_s": tau_s,
                         "p_hop": p_hop, "steps": steps, "sites": sysm.fields.n_sites,
                         "parts": {PARTS[r]: {"peak_ppm": float(peaks[r]),

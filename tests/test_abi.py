@@ -112,7 +112,7 @@ def test_max_p_hop_accepted(lib):
     assert st == N.LPC_OK
 
 
-def test_p_hop_from_residence_time():
+def test_p_hop_from_residence_time(lib):
     """A free site is left with probability 6 p_hop per step, so its mean residence time
     is dt / (6 p_hop): the 1 ms and 0.2 ms of the paper's runs at dt = 5 us."""
     from paper_2603_22553_amd.lattice import p_hop_from_residence_time

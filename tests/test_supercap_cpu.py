@@ -1,5 +1,5 @@
 """Host side of the supercapacitor workflow (section 4): the synthetic systems and the
-per-part diffusion formula, on the CPU."""
+per-part diffusion coefficients of the C ABI, on the CPU."""
 import numpy as np
 import pytest
 
@@ -42,9 +42,11 @@ def test_potential_moves_anions_and_shifts():
     assert np.allclose(dd[a.carbon], 3.0) and np.all(dd[~a.carbon] == 0.0)
 
 
-def test_part_diffusion_closed_form():
-    """Free-lattice moments: MSD grows by 2 p0 per step and axis, so D / D_bulk = 1."""
-    p0 = 1.0 / 240.0
+def test_region_diffusion_closed_form():
+    """lpc_region_diffusion (host-only, through the C ABI) on free-lattice moments: the MSD
+    grows by 2 p0 per step and axis (Eq. (7)), so D / D_bulk = 1 and D = p0 a^2 / dt."""
+    from paper_2603_22553_amd.lattice import region_diffusion
+    p0, dt, a = 1.0 / 240.0, 5e-6, 0.5e-9
     rho = np.array([5.0, 7.0, 11.0])
 
     def table(t):
@@ -53,7 +55,33 @@ def test_part_diffusion_closed_form():
         m[:, 4:7] = rho[:, None] * 2 * p0 * t
         return m
 
-    assert np.allclose(S.part_diffusion(table(100), table(350), 250, p0), 1.0)
+    D, ratio = region_diffusion(table(100), table(350), 250, p0, dt, a, axes=(0, 1))
+    assert np.allclose(ratio, 1.0, rtol=1e-14)
+    assert np.allclose(D, p0 * a * a / dt, rtol=1e-14)
+    # part 1 diffuses at half speed in the plane; z is not averaged in
     slow = table(350)
     slow[1, 4:6] = rho[1] * (2 * p0 * 100 + 0.5 * 2 * p0 * 250)
-    assert np.isclose(S.part_diffusion(table(100), slow, 250, p0)[1], 0.5)
+    slow[1, 6] = 0.0
+    _, ratio = region_diffusion(table(100), slow, 250, p0, dt, a, axes=(0, 1))
+    assert np.isclose(ratio[1], 0.5, rtol=1e-14) and np.allclose(ratio[[0, 2]], 1.0)
+    # one axis alone, and a population that changed between the tables (the MSD is per
+    # particle now in the part)
+    moved = table(350)
+    moved[2] *= 2.0
+    _, ratio = region_diffusion(table(100), moved, 250, p0, dt, a, axes=(2,))
+    assert np.allclose(ratio, 1.0, rtol=1e-14)
+
+
+def test_region_diffusion_errors():
+    from paper_2603_22553_amd import _native as N
+    from paper_2603_22553_amd.lattice import region_diffusion
+    t = np.ones((2, 7))
+    empty = t.copy()
+    empty[1, 0] = 0.0
+    for kw, status in ((dict(axes=()), N.LPC_ERR_ARG), (dict(steps_between=0), N.LPC_ERR_ARG),
+                       (dict(p_hop=0.0), N.LPC_ERR_ARG), (dict(sums_b=empty), N.LPC_ERR_STATE)):
+        args = dict(sums_a=t, sums_b=t, steps_between=10, p_hop=1 / 7)
+        args.update(kw)
+        with pytest.raises(N.LpcError) as e:
+            region_diffusion(**args)
+        assert e.value.status == status
