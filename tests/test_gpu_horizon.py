@@ -1,0 +1,50 @@
+"""The mixed path over the full horizon of the large-particle workload, against the oracle.
+
+The float-stored magnetisation and moments accumulate rounding step after step, so the FID
+and spectrum bounds of the mixed path (Eqs. (8)-(9): FID relative L2 <= 1e-3, spectral peaks
+within 0.01 ppm) are only tested where the run is as long as the workload's: 50 000 steps.
+The lattice is the workload's generator (pore-field correlation length 8 sites, widths
+0.7-2.0 nm, uniform start, periodic) at a size the oracle finishes in about a minute.
+"""
+import numpy as np
+import pytest
+
+from paper_2603_22553_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+DT, NU0, P0 = 5e-6, 400e6, 1.0 / 7.0
+
+
+def test_mixed_path_full_horizon(oracle):
+    from paper_2603_22553_amd.lattice import Lattice
+    f = synth.particle(40, 16, 8.0, (0.7, 2.0), seed=1)
+    steps = 50000
+    print(f"# oracle: 40^3 particle, {steps} steps", flush=True)
+    ref = oracle.run(f.F, f.delta, f.region, f.n_regions, steps)
+    print("# mixed path", flush=True)
+    with Lattice(f.shape_xyz, precision="mixed", n_regions=f.n_regions,
+                 max_records=steps + 1) as lat:
+        lat.set_fields(f)
+        lat.init_state("uniform")
+        lat.run(steps)
+        lat.check()
+        G = [lat.fid(r) for r in (None, 0, 1)]
+        peaks = [lat.peak_ppm(r) for r in (None, 0, 1)]
+        mass, msd, _ = lat.moments()
+        U = lat.uptake()
+        D, _ = lat.diffusion()
+    for k, r in enumerate((None, 0, 1)):
+        Go = ref.fid(r)
+        err = np.linalg.norm(G[k] - Go) / np.linalg.norm(Go)
+        assert err <= 1e-3, (r, err)
+        assert abs(peaks[k] - oracle.peak_ppm(Go, DT, NU0)) <= 0.01, r
+    # populations are double on the mixed path: conserved to 1e-12 over the whole run
+    assert np.max(np.abs(mass / mass[0] - 1.0)) <= 1e-12
+    # equilibrium uptake per region (the particle's share of the population) at every step
+    Uo = ref.uptake()
+    assert np.max(np.abs(U - Uo) / Uo.sum(axis=1, keepdims=True)) <= 1e-6
+    # moments: the MSD series and the diffusion coefficient of its second half
+    assert np.max(np.abs(msd - ref.msd())) <= 1e-4 * np.max(ref.msd())
+    Do, _ = oracle.diffusion(ref.msd(), DT, 0.5e-9)
+    np.testing.assert_allclose(D, Do, rtol=1e-4)
