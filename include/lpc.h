@@ -199,6 +199,26 @@ lpc_status lpc_spectrum_length(const lpc_lattice *lat, int64_t *n_fft);
 lpc_status lpc_spectrum(lpc_lattice *lat, int32_t region, int64_t n_fft, double *ppm, double *re,
                         double *im, int64_t cap);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving
+ * loops that must not allocate): the spectrum of lpc_spectrum for an FID already in device
+ * memory, computed in a work area of the library's own instead of a lattice's arena.
+ *  - fid: n_samples >= 1 complex samples on the device as interleaved (re, im) doubles. It
+ *    is divided by its first sample (a first sample of zero gives non-finite output),
+ *    zero-filled to n_fft points and transformed with exp(-2 pi i k n / n_fft) (Eq. (9)).
+ *  - n_fft: a power of two >= n_samples and <= 2^20; 0 selects the smallest power of two
+ *    >= 8 n_samples, which must then be <= 2^20.
+ *  - spec: 2 n_fft doubles on the device: the real parts in ascending frequency, then the
+ *    imaginary parts; bin j is at f_j = (j - n_fft/2) / (n_fft dt), as in lpc_spectrum.
+ * Queued on `stream` (hipStream_t as void*) and asynchronous. The work area is one static
+ * device array of 2^21 complex doubles (32 MiB) per device, held from the library's load
+ * until the process ends; nothing is allocated or freed. Every call on a device uses the
+ * same area, and each call writes it entirely before reading it: calls that overlap in
+ * time on one device (on different streams, or from several threads) race and must be
+ * serialised by the caller. LPC_ERR_ARG for NULL buffers, n_samples < 1, or n_fft not a
+ * power of two >= n_samples; LPC_ERR_OOM for n_fft beyond 2^20. */
+lpc_status lpc_spectrum_noalloc(const double *fid, int64_t n_samples, int64_t n_fft, double *spec,
+                                void *stream);
+
 /* Position in ppm of the maximum of Re F of the default-length spectrum, refined by the
  * vertex of the parabola through the highest bin and its two neighbours. */
 lpc_status lpc_spectrum_peak(lpc_lattice *lat, int32_t region, double *peak_ppm);

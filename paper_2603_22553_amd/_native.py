@@ -92,6 +92,7 @@ SIGNATURES = {
     "lpc_spectrum_length": [_P, _PI64],
     "lpc_spectrum": [_P, _I32, _I64, _P, _P, _P, _I64],
     "lpc_spectrum_peak": [_P, _I32, ctypes.POINTER(ctypes.c_double)],
+    "lpc_spectrum_noalloc": [_P, _I64, _I64, _P, _P],
     "lpc_diffusion": [_P, _P, _P],
     "lpc_uptake_profile": [_P, _I32, _P, _I64],
     "lpc_equilibrate": [_P, _I64, ctypes.c_double, _I64, _PI64, ctypes.POINTER(ctypes.c_double)],

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1592,6 +1593,67 @@ lpc_status lpc_batch_run(lpc_batch *batch, const int64_t *n_steps)
     LPC_HIP(hipEventRecord(batch->done, batch->stream));
     for (lpc_lattice *lat : batch->lats)
         LPC_HIP(hipStreamWaitEvent(lat->stream, batch->done, 0));
+    return ok();
+}
+
+}  // extern "C"
+
+namespace {
+
+// Work area of lpc_spectrum_noalloc: the two ping-pong buffers of the FFT at its largest
+// length. Each device holds its own copy from the library's load until the process ends.
+constexpr int64_t kNoallocFftMax = int64_t(1) << 20;
+static __device__ __align__(256) double2 scratch[2 * kNoallocFftMax];
+
+std::mutex g_scratch_mutex;
+std::vector<double2 *> g_scratch_ptr;   // device address of `scratch`, per device
+
+// Device address of the scratch array on the current device, looked up once per device.
+// The host-side name of the array is not a device address; only this pointer may reach a
+// kernel or a copy.
+lpc_status scratch_on_current_device(double2 **out)
+{
+    int dev = -1;
+    LPC_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch_ptr.size() <= size_t(dev))
+        g_scratch_ptr.resize(size_t(dev) + 1, nullptr);
+    if (!g_scratch_ptr[size_t(dev)]) {
+        void *p = nullptr;
+        LPC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p)
+            return fail(LPC_ERR_DEVICE, "no device address for the scratch area on device %d", dev);
+        g_scratch_ptr[size_t(dev)] = static_cast<double2 *>(p);
+    }
+    *out = g_scratch_ptr[size_t(dev)];
+    return LPC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lpc_status lpc_spectrum_noalloc(const double *fid, int64_t n_samples, int64_t n_fft, double *spec,
+                                void *stream)
+{
+    if (!fid || !spec)
+        return fail(LPC_ERR_ARG, "NULL buffer");
+    if (n_samples < 1)
+        return fail(LPC_ERR_ARG, "n_samples = %lld must be >= 1", (long long)n_samples);
+    const int64_t L = n_fft == 0 ? fft_length(n_samples) : n_fft;
+    if (L < n_samples || (L & (L - 1)) != 0)
+        return fail(LPC_ERR_ARG, "n_fft = %lld must be a power of two >= %lld samples",
+                    (long long)L, (long long)n_samples);
+    if (L > kNoallocFftMax)
+        return fail(LPC_ERR_OOM, "n_fft = %lld exceeds the scratch area's %lld points",
+                    (long long)L, (long long)kNoallocFftMax);
+    double2 *work = nullptr;
+    if (lpc_status s = scratch_on_current_device(&work))
+        return s;
+    // the FID as a record table of one region: K = 2 values (Re, Im) per row; the first
+    // kernel writes all L points of the first buffer, so nothing needs clearing
+    LPC_HIP(lpc::launch_fid_spectrum(fid, n_samples, 2, 1, -1, L, work, work + kNoallocFftMax,
+                                     spec, static_cast<hipStream_t>(stream)));
     return ok();
 }
 
