@@ -373,3 +373,107 @@ int lpc_oracle_equilibrate(int64_t nx, int64_t ny, int64_t nz, const int32_t *bc
     free(im);
     return 0;
 }
+
+/*
+ * Velocity autocorrelation of Eq. (4) (section 2.2) by moment propagation, independent of
+ * the displacement moments: C_a(tau) = <dx_a(1) dx_a(1 + tau)>, summed over the particles of
+ * the start rho (not normalised), tau = 0 .. n_lags - 1, for each axis a.
+ *  - C_a(0) = sum_i rho_i sum_j p(i->j) d_a(i->j)^2: the mean square of one step.
+ *  - A tag field carries each particle's first displacement: after the first step
+ *    V_a,i = sum_j p(j->i) d_a(j->i) rho_j (d_a of the move j -> i), and every later step
+ *    moves it like a population, V_a,i' = stay(i) V_a,i + sum_j p(j->i) V_a,j. A reservoir
+ *    ghost holds no tagged particle; moves into a ghost take their tag out of the lattice.
+ *  - After tau steps the tagged particles at i make their next move with mean displacement
+ *    v_a(i) = sum_j p(i->j) d_a(i->j), so C_a(tau) = sum_i V_a,i(tau) v_a(i) for tau >= 1.
+ * rho (n values) is not modified. C receives n_lags * 3 values (row tau: x, y, z).
+ * Returns 0, 1 (bad argument) or 2 (memory).
+ */
+int lpc_oracle_vacf(int64_t nx, int64_t ny, int64_t nz, const int32_t *bc, double p0,
+                    const double *F, const double *mobility, const double *ghost,
+                    const double *rho, int64_t n_lags, double *C)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || !F || !rho || !C || n_lags < 1 || bad_extras(bc, ghost))
+        return 1;
+    geometry g = {{nx, ny, nz}, {bc[0], bc[1], bc[2]}};
+    const int64_t n = nx * ny * nz;
+    double *V = calloc((size_t)(3 * n), sizeof(double));
+    double *W = malloc(sizeof(double) * 3 * n);
+    double *vel = malloc(sizeof(double) * 3 * n);   /* v_a(i) */
+    double *msq = malloc(sizeof(double) * 3 * n);   /* sum_j p(i->j) d_a^2 */
+    double *stay = malloc(sizeof(double) * n);
+    if (!V || !W || !vel || !msq || !stay) {
+        free(V); free(W); free(vel); free(msq); free(stay);
+        return 2;
+    }
+    /* per site: the mean displacement and mean square displacement of its next move, and
+     * its staying probability */
+    for (int64_t z = 0; z < nz; ++z)
+        for (int64_t y = 0; y < ny; ++y)
+            for (int64_t x = 0; x < nx; ++x) {
+                const int64_t i = x + nx * (y + ny * z);
+                double out = 0.0;
+                for (int a = 0; a < 3; ++a)
+                    vel[a * n + i] = msq[a * n + i] = 0.0;
+                if (!blocked(F[i]))
+                    for (int d = 0; d < 6; ++d) {
+                        const int64_t j = neighbour(&g, x, y, z, d);
+                        if (j == -1 || (j >= 0 && blocked(F[j])))
+                            continue;
+                        const double Fj = j >= 0 ? F[j] : ghost[4 * (-2 - j)];
+                        double alpha = 1.0;
+                        if (mobility)
+                            alpha = fmin(mobility[i], j >= 0 ? mobility[j] : 1.0);
+                        const double p = p0 * alpha * acceptance(F[i], Fj);
+                        out += p;
+                        for (int a = 0; a < 3; ++a) {
+                            vel[a * n + i] += p * HOP[d][a];
+                            msq[a * n + i] += p * HOP[d][a] * HOP[d][a];
+                        }
+                    }
+                stay[i] = 1.0 - out;
+            }
+    for (int a = 0; a < 3; ++a) {
+        double c0 = 0.0;
+        for (int64_t i = 0; i < n; ++i)
+            c0 += rho[i] * msq[a * n + i];
+        C[a] = c0;
+    }
+    /* gathers V' from V (first: the tagging step, with the displacement source d rho) */
+    for (int64_t tau = 1; tau < n_lags; ++tau) {
+        const int first = tau == 1;
+#pragma omp parallel for schedule(static)
+        for (int64_t z = 0; z < nz; ++z)
+            for (int64_t y = 0; y < ny; ++y)
+                for (int64_t x = 0; x < nx; ++x) {
+                    const int64_t i = x + nx * (y + ny * z);
+                    double in[3] = {0.0, 0.0, 0.0};
+                    if (!blocked(F[i]))
+                        for (int d = 0; d < 6; ++d) {
+                            const int64_t j = neighbour(&g, x, y, z, d);
+                            if (j < 0 || blocked(F[j]))
+                                continue;   /* closed face, obstacle, or an untagged ghost */
+                            double alpha = 1.0;
+                            if (mobility)
+                                alpha = fmin(mobility[i], mobility[j]);
+                            const double p_in = p0 * alpha * acceptance(F[j], F[i]);
+                            for (int a = 0; a < 3; ++a) {
+                                const double src = first ? -HOP[d][a] * rho[j] : V[a * n + j];
+                                in[a] += p_in * src;
+                            }
+                        }
+                    for (int a = 0; a < 3; ++a)
+                        W[a * n + i] = (first ? 0.0 : stay[i] * V[a * n + i]) + in[a];
+                }
+        double *t = V;
+        V = W;
+        W = t;
+        for (int a = 0; a < 3; ++a) {
+            double c = 0.0;
+            for (int64_t i = 0; i < n; ++i)
+                c += V[a * n + i] * vel[a * n + i];
+            C[3 * tau + a] = c;
+        }
+    }
+    free(V); free(W); free(vel); free(msq); free(stay);
+    return 0;
+}

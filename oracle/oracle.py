@@ -55,6 +55,8 @@ def _load():
         lib.lpc_oracle_threads.restype = ctypes.c_int
         lib.lpc_oracle_equilibrate.argtypes = [i64, i64, i64, P, d, P, P, P, P, d, i64, P, P]
         lib.lpc_oracle_equilibrate.restype = ctypes.c_int
+        lib.lpc_oracle_vacf.argtypes = [i64, i64, i64, P, d, P, P, P, P, i64, P]
+        lib.lpc_oracle_vacf.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -193,6 +195,27 @@ def equilibrate(F, n_max, tol, bc=(PERIODIC, PERIODIC, PERIODIC), p0=1.0 / 7.0, 
     if rc != 0:
         raise RuntimeError(f"oracle equilibration failed with code {rc}")
     return r.reshape(F.shape), int(steps.value), float(res.value)
+
+
+def vacf(F, n_lags, bc=(PERIODIC, PERIODIC, PERIODIC), p0=1.0 / 7.0, rho=None, mobility=None,
+         reservoir=None):
+    """Velocity autocorrelation of Eq. (4) by tag-field propagation: C[tau, a] =
+    <dx_a(1) dx_a(1 + tau)> per particle of the start `rho` (default: Boltzmann, Eq. (2)),
+    tau = 0 .. n_lags - 1. Independent of the displacement moments."""
+    lib = _load()
+    F = np.ascontiguousarray(F, dtype=np.float64)
+    nz, ny, nx = F.shape
+    r = boltzmann(F).reshape(-1) if rho is None else np.asarray(rho, dtype=np.float64).reshape(-1)
+    r = np.ascontiguousarray(np.where(accessible(F).reshape(-1), r, 0.0))
+    mob = None if mobility is None else np.ascontiguousarray(mobility, dtype=np.float64).reshape(-1)
+    gh = ghosts(reservoir)
+    C = np.zeros((n_lags, 3))
+    bc_arr = np.asarray(bc, dtype=np.int32)
+    rc = lib.lpc_oracle_vacf(nx, ny, nz, _ptr(bc_arr), p0, _ptr(F), _ptr(mob), _ptr(gh), _ptr(r),
+                             n_lags, _ptr(C))
+    if rc != 0:
+        raise RuntimeError(f"oracle autocorrelation failed with code {rc}")
+    return C / r.sum()
 
 
 # ---------------------------------------------------------------- post-processing (Eq. (9))

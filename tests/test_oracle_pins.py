@@ -248,6 +248,51 @@ def test_vacf_from_msd_second_difference(oracle):
         assert np.max(np.abs(got - C)) <= 1e-12 * C[0]
 
 
+def test_tag_vacf_equals_dense(oracle):
+    """Eq. (4) by a tag field (each particle carries its first displacement, propagated like
+    a population) against the dense C(tau) = 1^T T1 T0^(tau-1) T1 rho of the one-step
+    matrices, on every axis, with a closed axis, obstacles and link mobility."""
+    f = synth.random_fields((4, 4, 4), seed=43, F_scale=1.3)
+    F = f.F.copy()
+    F[0, 1, 2] = F[3, 2, 0] = np.inf
+    mu = np.random.default_rng(44).uniform(0.3, 1.0, size=F.shape)
+    t = 50
+    bc = (CLO, PER, PER)
+    got = oracle.vacf(F, t, bc=bc, mobility=mu)
+    rho_eq = _flat(oracle.boltzmann(F))
+    for a in range(3):
+        T0, T1, T2 = brute.matrices((4, 4, 4), bc, _flat(F), P0, axis=a, mobility=_flat(mu))
+        want = brute.vacf(T0, T1, T2, rho_eq, t) / rho_eq.sum()
+        assert np.max(np.abs(got[:, a] - want)) <= 1e-12 * want[0], a
+
+
+def test_tag_vacf_einstein_identity(oracle):
+    """From equilibrium, the displacement moments (propagated by the sweep's own recursion)
+    and the tag-field autocorrelation (a separate recursion) satisfy the Einstein sum:
+    MSD(t) = t C(0) + 2 sum_{tau<t} (t - tau) C(tau), at every t checked."""
+    f = synth.random_fields((5, 4, 6), seed=47, F_scale=1.0)
+    t = 120
+    bc = (PER, CLO, PER)
+    res = oracle.run(f.F, f.delta, f.region, 1, t, init="boltzmann", bc=bc)
+    C = oracle.vacf(f.F, t, bc=bc)
+    for a in range(3):
+        for tt in (1, 2, 7, 60, t):
+            want = brute.msd_from_vacf(C[:, a], tt)
+            assert abs(res.msd()[tt, a] - want) <= 1e-12 * want, (a, tt)
+
+
+def test_tag_vacf_free_lattice(oracle):
+    """F = 0, periodic: steps are independent, C(0) = 2 p0 (Eq. (7)) and C(tau >= 1) = 0; with
+    a closed axis the walls reflect: C(0) = 2 p0 (1 - 1/n) and the first lag is negative."""
+    F = np.zeros((6, 5, 7))
+    C = oracle.vacf(F, 20)
+    np.testing.assert_allclose(C[0], 2 * P0, rtol=1e-14)
+    assert np.max(np.abs(C[1:])) <= 1e-16
+    C = oracle.vacf(F, 20, bc=(CLO, PER, PER))
+    assert abs(C[0, 0] - 2 * P0 * (1 - 1 / 7)) <= 1e-14
+    assert C[1, 0] < 0 and np.max(np.abs(C[1:, 1:])) <= 1e-16
+
+
 # --------------------------------------------------------------------- P8a equilibration
 
 @pytest.mark.parametrize("bc", [(PER, PER, PER), (CLO, PER, CLO)])
