@@ -153,10 +153,17 @@ def run_timed(lat, steps, warmup, regions=(None,), msd=True):
 
 # ------------------------------------------------------------------- single large particle
 
-def run_particle(f, precision, steps, warmup, track=("fid", "msd")):
+def plan_for(precision, spp):
+    """lpc_set_plan arguments: two steps per pass (tile code 2) or the automatic one-step
+    plan."""
+    return (2, 0) if spp == 2 else (0, 0)
+
+
+def run_particle(f, precision, steps, warmup, track=("fid", "msd"), spp=1):
     from paper_2603_22553_amd.lattice import Lattice
     lat = Lattice(f.shape_xyz, precision=precision, track=track, n_regions=f.n_regions,
                   max_records=steps + warmup + 1)
+    lat.set_plan(*plan_for(precision, spp))
     lat.set_fields(f)
     lat.init_state("uniform")
     msd = "msd" in track
@@ -191,7 +198,9 @@ def particle_lines(f, args, precisions, track):
     full = track == ("fid", "msd")
     res, lines = {}, {}
     for p in precisions:
-        r = run_particle(f, p, args.steps_particle, args.warmup, track)
+        spp = steps_per_pass(args, p)
+        r = run_particle(f, p, args.steps_particle, args.warmup, track, spp)
+        r["spp"] = spp
         res[p] = r
         ms_p = r["ms"] / args.steps_particle
         print(f"# particle {p}: {r['gsu_s']:.2f} GSU/s, {ms_p:.4f} ms/step, {r['plan']}",
@@ -203,7 +212,7 @@ def particle_lines(f, args, precisions, track):
                                          traffic=measured_traffic(
                                              "sweep_particle_256cubed_hbm_traffic.md", p)
                                          if full else None),
-                    "plan": r["plan"],
+                    "plan": r["plan"], "steps_per_pass": r["spp"],
                     "results": {"mass_drift": r["mass_drift"], "peak_ppm": round(r["peak_ppm"], 5),
                                 "D_over_Dbulk": r["D_over_Dbulk"]}}
     if "fp64" in res and "mixed" in res:
@@ -219,6 +228,12 @@ def particle_lines(f, args, precisions, track):
                           if full else None),
             "steps": args.steps_particle + args.warmup}
     return lines
+
+
+def steps_per_pass(args, precision):
+    """Steps per sweep pass for a plain lattice: --steps-per-pass, or by default one (the
+    two-step kernel is slower on MI355X: it is bound by instruction issue, not by HBM)."""
+    return args.steps_per_pass or 1
 
 
 def workload_particle(args):
@@ -240,7 +255,7 @@ def workload_particle(args):
                                "particle, " + ("FID + MSD" if full else "FID only")
                                + " recorded every step, uniform start",
                    "sites": f.n_sites, "regions": f.n_regions, "precision": head,
-                   "steps_per_pass": 1, "plan": h["plan"]},
+                   "steps_per_pass": h["steps_per_pass"], "plan": h["plan"]},
         "roofline": h["roofline"], "post_ms": h["post_ms"], "results": h["results"],
     }
     line.update(lines)
@@ -280,16 +295,29 @@ def workload_batch(args):
         lats = []
         for f in fields:
             lat = Lattice(f.shape_xyz, precision=prec, n_regions=f.n_regions,
-                          max_records=steps + args.warmup + 1, batched=batched)
+                          max_records=2 * steps + args.warmup + 1, batched=batched)
             lat.set_fields(f)
             lat.init_state("uniform")
             lats.append(lat)
         return lats
 
     lats = make(True)
+    plans = None
+    if args.tune:
+        # one tuning per distinct box, timed in a batch of copies of itself
+        from paper_2603_22553_amd import autotune
+        t = time.perf_counter()
+        plans = autotune.apply_all(lats)
+        print(f"# tuned {len(plans)} box configurations in {time.perf_counter() - t:.1f} s",
+              file=sys.stderr, flush=True)
     batch = Batch(lats)
     batch.run(args.warmup)
+    # timed twice: launches replayed from captured graphs, then every step launched directly
+    # (the second run continues the same lattices, whose record rows hold both)
     _, ms = timed(batch.stream, lambda: batch.run(steps))
+    graph_desc = batch.describe()
+    batch.use_graph(False)
+    _, ms_direct = timed(batch.stream, lambda: batch.run(steps))
     batch.close()
     peaks = [lat.peak_ppm() for lat in lats[:4]]
     for lat in lats:
@@ -319,6 +347,12 @@ def workload_batch(args):
         "config": {"workload": f"{len(fields)} particles, radius 8-48, box 2R+8, one batched "
                                "sweep per step, FID + MSD", "sites": sites},
         "roofline": roofline(sites, prec, ms / steps),
+        "launch": graph_desc,
+        "direct_launches": {"value": round(sites * steps / (ms_direct * 1e-3) / 1e9, 4),
+                            "unit": "GSU/s", "ms_per_step": round(ms_direct / steps, 6),
+                            "note": "the same batch with every step launched directly"},
+        "plans": ({f"{'x'.join(map(str, c[0]))}": list(v) for c, v in plans.items()}
+                  if plans else "automatic (batch plans)"),
         "alone": {"value": round(gsu_alone, 4), "unit": "GSU/s",
                   "ms_per_step": round(ms_alone / steps, 6),
                   "note": "same particles stepped one lattice at a time, on solo plans"},
@@ -340,6 +374,8 @@ def workload_film(args):
     bc = ("closed", "periodic", "periodic")
     lat = Lattice(f.shape_xyz, bc=bc, precision="mixed", n_regions=3,
                   max_records=steps + args.warmup + 1)
+    spp = steps_per_pass(args, "mixed")
+    lat.set_plan(*plan_for("mixed", spp))
     lat.set_fields(f)
     lat.init_state("boltzmann")
     ms, ms_post, peaks, D, ratio = run_timed(lat, steps, args.warmup, regions=(0, 1, 2))
@@ -361,7 +397,7 @@ def workload_film(args):
                                "768 sites, closed in x, periodic in y and z, Boltzmann start, "
                                "FID per region + MSD recorded every step",
                    "sites": f.n_sites, "regions": 3, "precision": "mixed",
-                   "steps_per_pass": 1, "plan": plan},
+                   "steps_per_pass": spp, "plan": plan},
         "roofline": roofline(f.n_sites, "mixed", ms_step, n_regions=3,
                              traffic=measured_traffic("sweep_film_2048x256x256_hbm_traffic.md",
                                                       "mixed")),
@@ -715,9 +751,15 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=None,
                     help="oracle steps timed for the CPU baseline (0 skips it; default 12 on "
                          "the film, 20 on the particle)")
+    ap.add_argument("--steps-per-pass", type=int, choices=[0, 1, 2], default=0,
+                    help="sweep steps per pass (temporal blocking) on the film and particle "
+                         "workloads; 0: one")
     ap.add_argument("--particle-steps", type=int, default=2000,
                     help="film workload: steps of the 256^3 particle timed beside it (0 skips)")
     ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--tune", type=int, default=1,
+                    help="batch workload: plans from the autotuner (each distinct box timed in a "
+                         "batch of copies); 0: the automatic batch plans")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-alone", type=int, default=20)

@@ -80,8 +80,11 @@ enum { LPC_OPT_MOBILITY = 1u, LPC_OPT_BATCHED = 2u };
  * every record sum in double. */
 enum { LPC_PREC_FP64 = 0, LPC_PREC_MIXED = 1 };
 
-/* Track set. Populations are always propagated. */
-enum { LPC_TRACK_FID = 1u, LPC_TRACK_MSD = 2u };
+/* Track set. Populations are always propagated. FID: the magnetisation; MSD: the
+ * displacement moments M1, M2 per axis; VACF (with MSD): three more fields that carry each
+ * particle's first displacement, from which the velocity autocorrelation of Eq. (4) is
+ * recorded every step without differencing the moments (lpc_read_vacf). */
+enum { LPC_TRACK_FID = 1u, LPC_TRACK_MSD = 2u, LPC_TRACK_VACF = 4u };
 
 enum { LPC_INIT_UNIFORM = 0, LPC_INIT_BOLTZMANN = 1, LPC_INIT_USER = 2 };
 
@@ -162,8 +165,10 @@ lpc_status lpc_run(lpc_lattice *lat, int64_t n_steps);
 lpc_status lpc_synchronize(lpc_lattice *lat);
 lpc_status lpc_steps_done(const lpc_lattice *lat, int64_t *n);
 
-/* Record width K = 3 R + 6 and raw records: rows of [Re G_r, Im G_r] (r < R),
- * U_r (r < R), S1_x, S1_y, S1_z, S2_x, S2_y, S2_z; row t is after t steps. */
+/* Record width K = 3 R + 6 (+ 3 with LPC_TRACK_VACF) and raw records: rows of
+ * [Re G_r, Im G_r] (r < R), U_r (r < R), S1_x, S1_y, S1_z, S2_x, S2_y, S2_z, then with the
+ * tags C_x, C_y, C_z; row t is after t steps. C of row t >= 1 is the sum over particles of
+ * dx_a(1) dx_a(t) (the lag t - 1 of lpc_read_vacf, not normalised); row 0 holds zeros. */
 lpc_status lpc_record_width(const lpc_lattice *lat, int32_t *K);
 lpc_status lpc_read_records(lpc_lattice *lat, double *records, int64_t cap_rows, int64_t *rows);
 
@@ -230,13 +235,18 @@ lpc_status lpc_spectrum_peak(lpc_lattice *lat, int32_t region, double *peak_ppm)
 lpc_status lpc_diffusion(lpc_lattice *lat, double *D_m2_s, double *ratio);
 
 /* Discrete velocity autocorrelation of Eq. (4) per axis, C(0) = <dx_1^2> and
- * C(tau) = <dx_1 dx_{1+tau}>, for tau = 0..N-1, from the recorded mean-square displacement
- * through the identity of a stationary increment process, MSD(t) = t C(0) +
- * 2 sum_{tau=1}^{t-1} (t - tau) C(tau): C(0) = MSD(1) - MSD(0), C(tau) = (MSD(tau+1) -
- * 2 MSD(tau) + MSD(tau-1)) / 2. Valid for runs started from equilibrium (Boltzmann start, or
- * after lpc_equilibrate). The Kohn estimate of Eq. (4) truncated at lag T is then
- * D_a(T) = a^2 [C(0)/2 + sum_{tau=1}^{T} C(tau)] / dt_s. Writes N rows of 3 values (lattice
- * units^2); needs LPC_TRACK_MSD and N >= 2. */
+ * C(tau) = <dx_1 dx_{1+tau}> per particle of the start, for tau = 0..N-1. With
+ * LPC_TRACK_VACF it is measured directly: every particle carries its first displacement in a
+ * tag field (set on the first step after a start, then moved like a population), and each
+ * step records sum_i V_a,i v_a(i), where v_a(i) is the mean displacement of the next move
+ * from site i (on the first step, sum_i rho_i <dx_a^2>_i); C is that record over the initial
+ * population. Without it, C is taken from the recorded mean-square displacement through the
+ * identity of a stationary increment process, MSD(t) = t C(0) + 2 sum_{tau=1}^{t-1} (t - tau)
+ * C(tau): C(0) = MSD(1) - MSD(0), C(tau) = (MSD(tau+1) - 2 MSD(tau) + MSD(tau-1)) / 2. Both
+ * are meant for runs started from equilibrium (Boltzmann start, or after lpc_equilibrate),
+ * where the two agree; the tags need no stationarity. The Kohn estimate of Eq. (4)
+ * truncated at lag T is D_a(T) = a^2 [C(0)/2 + sum_{tau=1}^{T} C(tau)] / dt_s. Writes N rows
+ * of 3 values (lattice units^2); needs LPC_TRACK_MSD and N >= 2. */
 lpc_status lpc_read_vacf(lpc_lattice *lat, double *vacf_xyz, int64_t cap, int64_t *len);
 
 /* Kohn estimate of the diffusion coefficient, Eq. (4) (section 2.2): the discrete velocity
@@ -287,8 +297,9 @@ lpc_status lpc_load_state(lpc_lattice *lat, const void *buf, size_t len);
 
 /* Batches: many lattices stepped together (independent particles of different sizes).
  * Every step is one launch per tile width covering the tiles of all lattices that still
- * have steps left; each lattice keeps its own tiles and reduction order, so its state and
- * records end bit for bit as if it had been run alone with lpc_run. */
+ * have steps left, replayed from captured graphs (lpc_batch_use_graph); each lattice keeps
+ * its own tiles and reduction order, so its state and records end bit for bit as if it had
+ * been run alone with lpc_run on its one-step plan. */
 
 /* Device bytes the work tables of a batch of `count` lattices need. */
 lpc_status lpc_batch_query_footprint(int32_t count, size_t *bytes);
@@ -306,6 +317,19 @@ lpc_status lpc_batch_destroy(lpc_batch *batch);
  * queued then). Synchronizes the stream each time the set of lattices still stepping
  * changes (to rewrite the work tables); otherwise asynchronous. */
 lpc_status lpc_batch_run(lpc_batch *batch, const int64_t *n_steps);
+
+/* Whether lpc_batch_run replays captured graphs (enable != 0, the default) or launches every
+ * step itself. With graphs, the launches of one chunk of steps (an even number, up to the
+ * steps whose partial sums the lattices hold together) are recorded once per phase (a stretch
+ * in which the set of lattices still stepping does not change) into a HIP graph, which is
+ * then launched once per chunk on the batch's stream; the remaining steps of a phase are
+ * launched directly. The kernels, their arguments and their order are the same either way,
+ * so the results are bit for bit the same. */
+lpc_status lpc_batch_use_graph(lpc_batch *batch, int32_t enable);
+
+/* The batch's launch mode and counters (chunks replayed from graphs, steps launched
+ * directly) as text, NUL-terminated and truncated to cap bytes. */
+lpc_status lpc_batch_describe(const lpc_batch *batch, char *buf, size_t cap);
 
 /* Calibration utility: copies `bytes` bytes from device buffer src to device buffer dst
  * (16-byte aligned, non-overlapping) with a plain streaming kernel on `stream`, so that
@@ -342,6 +366,16 @@ lpc_status lpc_stream_columns_mixed(const double *rho_in, const float *const *in
  * reservoir axis. */
 #define LPC_TILE_LINEAR 1
 
+/* tile_x of lpc_set_plan for temporal blocking, two steps per sweep pass: each pass reads
+ * the state and the fields once and writes the state once for two steps, so a step moves
+ * about half the HBM bytes of a one-step pass. A workgroup takes the first step on a block of
+ * 32 x 8 columns and the second on the inner 30 x 6 columns it owns (the first step of the
+ * ring is repeated by the neighbouring tiles). The state after any number of steps is bit
+ * for bit that of one step per pass; the per-step sums are taken over other tiles and agree
+ * to rounding. A run of an odd number of steps ends with a one-step pass. Available for the
+ * plain variant (no mobility field, no reservoir axis); batches step one step per pass. */
+#define LPC_TILE_TWO_STEP 2
+
 /* Widest x extent (nx) that lattices of this configuration's precision, track set and
  * variant can run on linear tiles, in *max_nx (0: none; lattices with a mobility field or a
  * reservoir axis run block tiles only). Host-only: needs no device. LPC_ERR_ARG for an
@@ -349,9 +383,10 @@ lpc_status lpc_stream_columns_mixed(const double *rho_in, const float *const *in
 lpc_status lpc_query_linear_tiles(const lpc_config *cfg, int32_t *max_nx);
 
 /* Overrides the launch plan of the sweep: tile_x 64, 32 or 16 columns per tile row,
- * LPC_TILE_LINEAR, or 0 (automatic: the block width with the least padding in x within
- * 1.5x, or linear tiles where they leave fewer lanes idle and are available), and zc planes
- * per workgroup (0: chosen from the device's resident workgroups). Any plan computes the
+ * LPC_TILE_LINEAR, LPC_TILE_TWO_STEP (two steps per pass), or 0 (automatic: one step per
+ * pass, the block width with the least padding in x within 1.5x, or linear tiles where they
+ * leave fewer lanes idle and are available), and zc planes per workgroup (0: chosen from the
+ * device's resident workgroups). Any plan computes the
  * same step; the plan fixes the order of the per-step sums, so results are bitwise
  * reproducible for a given plan and agree to rounding across plans. LPC_ERR_ARG if the
  * plan's partial sums do not fit the arena, or linear tiles are asked for where they are

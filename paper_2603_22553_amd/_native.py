@@ -20,7 +20,7 @@ BC_PERIODIC, BC_CLOSED, BC_RESERVOIR = 0, 1, 2
 OPT_MOBILITY = 1
 OPT_BATCHED = 2
 PREC_FP64, PREC_MIXED = 0, 1
-TRACK_FID, TRACK_MSD = 1, 2
+TRACK_FID, TRACK_MSD, TRACK_VACF = 1, 2, 4
 INIT_UNIFORM, INIT_BOLTZMANN, INIT_USER = 0, 1, 2
 MAX_REGIONS = 8
 
@@ -107,6 +107,8 @@ SIGNATURES = {
     "lpc_batch_create": [_P, _I32, _P, _SZ, _P, ctypes.POINTER(_P)],
     "lpc_batch_destroy": [_P],
     "lpc_batch_run": [_P, _P],
+    "lpc_batch_use_graph": [_P, _I32],
+    "lpc_batch_describe": [_P, ctypes.c_char_p, _SZ],
 }
 
 

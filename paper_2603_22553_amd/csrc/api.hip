@@ -74,12 +74,12 @@ struct Layout {
     lpc::SweepPlan plan{};
     int64_t chunk = 1;
     int64_t staging = 0;
-    size_t off_F = 0, off_theta = 0, off_region = 0, off_mu = 0, off_ghost = 0, off_partials = 0,
+    size_t off_F = 0, off_E = 0, off_theta = 0, off_region = 0, off_mu = 0, off_ghost = 0, off_partials = 0,
            off_records = 0, off_staging = 0, off_scalars = 0, off_fft = 0, off_argmax = 0,
            off_profile = 0, off_list = 0, off_regsum = 0;
     int64_t fft_max = 0;
     size_t off_rho[2] = {0, 0}, off_re[2] = {0, 0}, off_im[2] = {0, 0};
-    size_t off_m1[2][3] = {}, off_m2[2][3] = {};
+    size_t off_m1[2][3] = {}, off_m2[2][3] = {}, off_v[2][3] = {};
     size_t partial_bytes = 0;
     size_t total = 0;
 };
@@ -92,6 +92,15 @@ void set_chunk(Layout &L)
     L.chunk = std::max<int64_t>(1, std::min<int64_t>(kChunkMax, c));
 }
 
+// Steps of two-step passes finalised together: an even count whose partials fit the buffer
+// (which holds at least two steps of the largest plan).
+int64_t two_step_chunk(const Layout &L, const lpc::SweepPlan &p2)
+{
+    const int64_t per_step = int64_t(L.K) * std::max<int64_t>(1, p2.nblocks) * 8;
+    const int64_t c = std::min<int64_t>(kChunkMax, int64_t(L.partial_bytes) / per_step);
+    return std::max<int64_t>(2, c - c % 2);
+}
+
 bool fid_of(const lpc_config &c)
 {
     return (c.track & LPC_TRACK_FID) != 0;
@@ -99,6 +108,16 @@ bool fid_of(const lpc_config &c)
 bool msd_of(const lpc_config &c)
 {
     return (c.track & LPC_TRACK_MSD) != 0;
+}
+bool vacf_of(const lpc_config &c)
+{
+    return (c.track & LPC_TRACK_VACF) != 0;
+}
+// Record width: per region Re/Im G and U, then S1 and S2 per axis, then (with the tags) the
+// velocity autocorrelation per axis.
+int record_width_of(const lpc_config &c)
+{
+    return 3 * c.n_regions + 6 + (vacf_of(c) ? 3 : 0);
 }
 bool mobility_of(const lpc_config &c)
 {
@@ -121,6 +140,13 @@ uint32_t variant_of(const lpc_config &c)
     return c.track | (mobility_of(c) || reservoir_of(c) ? lpc::kVariantExtended : 0u);
 }
 
+// Two steps per pass are built for the plain variant (no mobility field, no reservoir axis)
+// without autocorrelation tags.
+bool two_step_available(const lpc_config &c)
+{
+    return !(variant_of(c) & lpc::kVariantExtended) && !vacf_of(c);
+}
+
 lpc_status validate_config(const lpc_config *c)
 {
     if (!c)
@@ -137,8 +163,10 @@ lpc_status validate_config(const lpc_config *c)
         return fail(LPC_ERR_ARG, "nx * ny must not exceed 2^28 (one z-plane of doubles < 2 GiB)");
     if (c->precision != LPC_PREC_FP64 && c->precision != LPC_PREC_MIXED)
         return fail(LPC_ERR_ARG, "precision %d unknown", c->precision);
-    if (c->track & ~uint32_t(LPC_TRACK_FID | LPC_TRACK_MSD))
+    if (c->track & ~uint32_t(LPC_TRACK_FID | LPC_TRACK_MSD | LPC_TRACK_VACF))
         return fail(LPC_ERR_ARG, "track bits 0x%x unknown", c->track);
+    if ((c->track & LPC_TRACK_VACF) && !(c->track & LPC_TRACK_MSD))
+        return fail(LPC_ERR_ARG, "LPC_TRACK_VACF needs LPC_TRACK_MSD");
     if (c->n_regions < 1 || c->n_regions > LPC_MAX_REGIONS)
         return fail(LPC_ERR_ARG, "n_regions = %d outside 1..%d", c->n_regions, LPC_MAX_REGIONS);
     if (c->options & ~uint32_t(LPC_OPT_MOBILITY | LPC_OPT_BATCHED))
@@ -164,6 +192,10 @@ struct SoloTables {
     int64_t kprefix[2];
     lpc::SweepItem eq_item;      // the population-only sweep of lpc_equilibrate
     int64_t eq_prefix[2];
+    lpc::SweepItem item_tag;     // the first step after a start: sets the autocorrelation tags
+    lpc::SweepItem item2;        // the two-step sweep (plans of two steps per pass)
+    int64_t prefix2[2];
+    lpc::FinalizeItem fin2;
 };
 
 // Buffer placement for cfg. The sweep plan depends on the device (resident workgroups per
@@ -173,7 +205,7 @@ Layout plan_layout(const lpc_config &c)
 {
     Layout L;
     L.n = int64_t(c.n[0]) * c.n[1] * c.n[2];
-    L.K = 3 * c.n_regions + 6;
+    L.K = record_width_of(c);
     L.storage = c.precision == LPC_PREC_FP64 ? 8 : 4;
     lpc::Geometry g{c.n[0], c.n[1], c.n[2], {c.bc[0], c.bc[1], c.bc[2]}};
     L.plan = lpc::make_plan(g, 1, 256, 0, lpc::linear_tile_max_nx(c.precision, variant_of(c)),
@@ -188,6 +220,8 @@ Layout plan_layout(const lpc_config &c)
     };
     const size_t ns = size_t(L.n) * L.storage;
     L.off_F = take(ns);
+    // FP64 path: the Boltzmann factors e^{F - c} the sweep reads
+    L.off_E = take(c.precision == LPC_PREC_FP64 ? ns : 0);
     L.off_theta = take(fid_of(c) ? ns : 0);
     L.off_region = take(size_t(L.n));
     L.off_mu = take(mobility_of(c) ? ns : 0);
@@ -199,9 +233,10 @@ Layout plan_layout(const lpc_config &c)
         for (int a = 0; a < 3; ++a) {
             L.off_m1[b][a] = take(msd_of(c) ? ns : 0);
             L.off_m2[b][a] = take(msd_of(c) ? ns : 0);
+            L.off_v[b][a] = take(vacf_of(c) ? ns : 0);
         }
     }
-    L.partial_bytes = size_t(std::max<int64_t>(kPartialBudget, per_step_max));
+    L.partial_bytes = size_t(std::max<int64_t>(kPartialBudget, 2 * per_step_max));
     L.off_partials = take(L.partial_bytes);
     L.off_records = take(size_t(c.max_records) * L.K * 8);
     L.off_staging = take(size_t(L.staging) * 8);
@@ -238,6 +273,12 @@ struct lpc_lattice {
     // Their partial sums are discarded, so the plan fixes no result.
     lpc::SweepPlan eq_plan{};
     int occupancy = 1, cus = 1;      // resident sweep workgroups per CU, compute units
+    // Temporal blocking: steps per sweep pass (1, or 2 with the two-step plan), the plan of
+    // the two-step kernel, its resident workgroups per CU and the steps finalised together.
+    int32_t steps_per_pass = 1;
+    lpc::SweepPlan plan2{};
+    int occupancy2 = 0;
+    int64_t chunk2 = 2;
 
     template <typename T = void>
     T *at(size_t off) const
@@ -257,12 +298,12 @@ struct lpc_lattice {
         return it;
     }
 
-    lpc::FinalizeItem finalize_item(int64_t row_base) const
+    lpc::FinalizeItem finalize_item(int64_t row_base, int64_t nblocks = -1) const
     {
         lpc::FinalizeItem f{};
         f.partials = partials();
         f.records = records();
-        f.nblocks = L.plan.nblocks;
+        f.nblocks = nblocks < 0 ? L.plan.nblocks : nblocks;
         f.row_base = row_base;
         f.K = L.K;
         return f;
@@ -280,7 +321,7 @@ struct lpc_lattice {
         a.K = L.K;
         a.p0 = cfg.p_hop;
         a.fc = Fmid;
-        a.F = at(L.off_F);
+        a.F = at(cfg.precision == LPC_PREC_FP64 ? L.off_E : L.off_F);
         a.theta = at(L.off_theta);
         a.region = at<uint8_t>(L.off_region);
         a.mu = mobility_of(cfg) ? at(L.off_mu) : nullptr;
@@ -318,6 +359,13 @@ SoloTables solo_tables(const lpc_lattice *lat)
     tables.eq_item.plan = lat->eq_plan;
     tables.eq_prefix[0] = 0;
     tables.eq_prefix[1] = lat->eq_plan.nblocks;
+    tables.item_tag = tables.item;
+    tables.item_tag.a.tag = 1;
+    tables.item2 = tables.item;
+    tables.item2.plan = lat->plan2;
+    tables.prefix2[0] = 0;
+    tables.prefix2[1] = lat->plan2.nblocks;
+    tables.fin2 = lat->finalize_item(0, lat->plan2.nblocks);
     return tables;
 }
 
@@ -430,6 +478,8 @@ size_t state_bytes(const lpc_lattice *lat)
         b += 2 * size_t(n) * lat->L.storage;
     if (msd_of(lat->cfg))
         b += 6 * size_t(n) * lat->L.storage;
+    if (vacf_of(lat->cfg))
+        b += 3 * size_t(n) * lat->L.storage;
     return b;
 }
 
@@ -512,12 +562,19 @@ lpc_status lpc_create(const lpc_config *cfg, void *arena, size_t arena_bytes, vo
         lat->L.plan = lpc::make_plan(g, occ, cus, 0,
                                      lpc::linear_tile_max_nx(cfg->precision, variant_of(*cfg)),
                                      zc_floor(*cfg));
-        const uint32_t pop = variant_of(*cfg) & ~uint32_t(LPC_TRACK_FID | LPC_TRACK_MSD);
+        const uint32_t pop =
+            variant_of(*cfg) & ~uint32_t(LPC_TRACK_FID | LPC_TRACK_MSD | LPC_TRACK_VACF);
         lat->eq_plan = lpc::make_plan(g, lpc::sweep_blocks_per_cu(cfg->precision, pop,
                                                                  cfg->n_regions),
                                       cus, 0, lpc::linear_tile_max_nx(cfg->precision, pop),
                                       zc_floor(*cfg));
         set_chunk(lat->L);
+        if (two_step_available(*cfg)) {
+            lat->occupancy2 = lpc::sweep_blocks_per_cu(cfg->precision, variant_of(*cfg),
+                                                       cfg->n_regions, 2);
+            lat->plan2 = lpc::make_plan2(g, lat->occupancy2, cus, zc_floor(*cfg));
+            lat->chunk2 = two_step_chunk(lat->L, lat->plan2);
+        }
     }
     for (int b = 0; b < 2; ++b) {
         lpc::StateView &v = lat->st[b];
@@ -527,6 +584,7 @@ lpc_status lpc_create(const lpc_config *cfg, void *arena, size_t arena_bytes, vo
         for (int a = 0; a < 3; ++a) {
             v.m1[a] = msd_of(*cfg) ? lat->at(L.off_m1[b][a]) : nullptr;
             v.m2[a] = msd_of(*cfg) ? lat->at(L.off_m2[b][a]) : nullptr;
+            v.v[a] = vacf_of(*cfg) ? lat->at(L.off_v[b][a]) : nullptr;
         }
     }
     const size_t ns = size_t(L.n) * L.storage;
@@ -534,6 +592,8 @@ lpc_status lpc_create(const lpc_config *cfg, void *arena, size_t arena_bytes, vo
     hipError_t e = hipMemcpy(lat->solo(), &tables, sizeof tables, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemsetAsync(lat->at(L.off_F), 0, ns, lat->stream);
+    if (e == hipSuccess && cfg->precision == LPC_PREC_FP64)   // e^{0 - 0} of the cleared field
+        e = lpc::launch_fill_field(cfg->precision, lat->at(L.off_E), L.n, 1.0, lat->stream);
     if (e == hipSuccess && fid_of(*cfg))
         e = hipMemsetAsync(lat->at(L.off_theta), 0, ns, lat->stream);
     if (e == hipSuccess)
@@ -604,6 +664,13 @@ lpc_status lpc_set_free_energy(lpc_lattice *lat, const double *F_kT, int64_t n)
     lat->Fmin = open > 0 ? fmin : 0.0;
     lat->Fmid = open > 0 ? 0.5 * (fmin + fmax) : 0.0;
     lat->n_open = open;
+    if (lat->cfg.precision == LPC_PREC_FP64) {
+        LPC_HIP(lpc::launch_boltzmann_factors(lat->at<double>(lat->L.off_F),
+                                              lat->at<double>(lat->L.off_E), lat->L.n, lat->Fmid,
+                                              lat->stream));
+        if (lpc_status s = sync(lat))
+            return s;
+    }
     if (lpc_status s = upload_solo(lat))
         return s;
     return ok();
@@ -739,6 +806,59 @@ lpc_status lpc_init_state(lpc_lattice *lat, int32_t mode, const double *rho, int
     return ok();
 }
 
+}  // extern "C"
+
+namespace {
+
+// Queues n_steps steps of a lattice alone on stream s (its own stream, or a batch's), with
+// the finalisation of their records. The first step after a start sets the autocorrelation
+// tags (lattices that track them).
+lpc_status queue_steps(lpc_lattice *lat, int64_t n_steps, hipStream_t stream)
+{
+    SoloTables *t = lat->solo();
+    int64_t left = n_steps;
+    if (lat->steps_per_pass == 2) {
+        // pairs of steps, one two-step pass each; an odd last step takes a one-step pass
+        lpc::StepList list2{&t->item2, t->prefix2, 1, lpc::kTileTwoStep, lat->plan2.nblocks, 0, 0};
+        while (left >= 2) {
+            const int64_t c = std::min(left - left % 2, lat->chunk2);
+            for (int64_t s = 0; s < c; s += 2) {
+                list2.parity = lat->cur;
+                list2.slot = s;
+                LPC_HIP(lpc::launch_step_list(list2, lat->cfg.precision, variant_of(lat->cfg),
+                                              lat->cfg.n_regions, stream));
+                lat->cur ^= 1;
+            }
+            LPC_HIP(lpc::launch_finalize_list(&t->fin2, t->kprefix, 1, lat->L.K, c,
+                                              lat->steps_done + 1, stream));
+            lat->steps_done += c;
+            left -= c;
+        }
+    }
+    const bool tags = vacf_of(lat->cfg);
+    lpc::StepList list{&t->item, t->prefix, 1, lat->L.plan.tx, lat->L.plan.nblocks, 0, 0};
+    while (left > 0) {
+        const int64_t c = left < lat->L.chunk ? left : lat->L.chunk;
+        for (int64_t s = 0; s < c; ++s) {
+            list.items = tags && lat->steps_done + s == 0 ? &t->item_tag : &t->item;
+            list.parity = lat->cur;
+            list.slot = s;
+            LPC_HIP(lpc::launch_step_list(list, lat->cfg.precision, variant_of(lat->cfg),
+                                          lat->cfg.n_regions, stream));
+            lat->cur ^= 1;
+        }
+        LPC_HIP(lpc::launch_finalize_list(&t->fin, t->kprefix, 1, lat->L.K, c,
+                                          lat->steps_done + 1, stream));
+        lat->steps_done += c;
+        left -= c;
+    }
+    return LPC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 lpc_status lpc_run(lpc_lattice *lat, int64_t n_steps)
 {
     if (!lat)
@@ -753,24 +873,7 @@ lpc_status lpc_run(lpc_lattice *lat, int64_t n_steps)
                     (long long)n_steps);
     if (lpc_status s = use_device(lat))
         return s;
-    SoloTables *t = lat->solo();
-    lpc::StepList list{&t->item, t->prefix, 1, lat->L.plan.tx, lat->L.plan.nblocks, 0, 0};
-    int64_t left = n_steps;
-    while (left > 0) {
-        const int64_t c = left < lat->L.chunk ? left : lat->L.chunk;
-        for (int64_t s = 0; s < c; ++s) {
-            list.parity = lat->cur;
-            list.slot = s;
-            LPC_HIP(lpc::launch_step_list(list, lat->cfg.precision, variant_of(lat->cfg),
-                                          lat->cfg.n_regions, lat->stream));
-            lat->cur ^= 1;
-        }
-        LPC_HIP(lpc::launch_finalize_list(&t->fin, t->kprefix, 1, lat->L.K, c,
-                                          lat->steps_done + 1, lat->stream));
-        lat->steps_done += c;
-        left -= c;
-    }
-    return ok();
+    return queue_steps(lat, n_steps, lat->stream);
 }
 
 lpc_status lpc_equilibrate(lpc_lattice *lat, int64_t max_steps, double tol, int64_t check_every,
@@ -801,8 +904,9 @@ lpc_status lpc_equilibrate(lpc_lattice *lat, int64_t max_steps, double tol, int6
         for (int64_t s = 0; s < c; ++s) {
             list.parity = lat->cur;
             LPC_HIP(lpc::launch_step_list(list, lat->cfg.precision,
-                                          variant_of(lat->cfg) & ~uint32_t(LPC_TRACK_FID |
-                                                                          LPC_TRACK_MSD),
+                                          variant_of(lat->cfg) &
+                                              ~uint32_t(LPC_TRACK_FID | LPC_TRACK_MSD |
+                                                        LPC_TRACK_VACF),
                                           lat->cfg.n_regions, lat->stream));
             lat->cur ^= 1;
         }
@@ -1063,6 +1167,12 @@ lpc_status lpc_save_state(lpc_lattice *lat, void *buf, size_t cap, size_t *len)
             p += ns;
         }
     }
+    if (vacf_of(lat->cfg)) {
+        for (int a = 0; a < 3; ++a) {
+            LPC_HIP(hipMemcpy(p, v.v[a], ns, hipMemcpyDeviceToHost));
+            p += ns;
+        }
+    }
     LPC_HIP(hipMemcpy(p, lat->records(), size_t(rows) * lat->L.K * 8, hipMemcpyDeviceToHost));
     *len = need;
     return ok();
@@ -1113,6 +1223,12 @@ lpc_status lpc_load_state(lpc_lattice *lat, const void *buf, size_t len)
         }
         for (int a = 0; a < 3; ++a) {
             LPC_HIP(hipMemcpy(v.m2[a], p, ns, hipMemcpyHostToDevice));
+            p += ns;
+        }
+    }
+    if (vacf_of(lat->cfg)) {
+        for (int a = 0; a < 3; ++a) {
+            LPC_HIP(hipMemcpy(v.v[a], p, ns, hipMemcpyHostToDevice));
             p += ns;
         }
     }
@@ -1283,12 +1399,25 @@ lpc_status lpc_read_vacf(lpc_lattice *lat, double *vacf_xyz, int64_t cap, int64_
     if (lpc_status s = health(lat, rec))
         return s;
     const int K = lat->L.K, R = lat->cfg.n_regions;
-    auto msd = [&](int64_t t, int a) {
+    auto mass = [&](int64_t t) {
         double m = 0.0;
         for (int r = 0; r < R; ++r)
             m += rec[size_t(t * K + 2 * R + r)];
-        return rec[size_t(t * K + 3 * R + 3 + a)] / m;
+        return m;
     };
+    if (vacf_of(lat->cfg)) {
+        // the tag sums: row t + 1 holds sum over particles of dx_1 dx_{1+t}; per particle of the
+        // start
+        const double m0 = mass(0);
+        if (m0 == 0.0)
+            return fail(LPC_ERR_STATE, "the lattice holds no population");
+        for (int64_t tau = 0; tau < N; ++tau)
+            for (int a = 0; a < 3; ++a)
+                vacf_xyz[3 * tau + a] = rec[size_t((tau + 1) * K + 3 * R + 6 + a)] / m0;
+        *len = N;
+        return ok();
+    }
+    auto msd = [&](int64_t t, int a) { return rec[size_t(t * K + 3 * R + 3 + a)] / mass(t); };
     for (int a = 0; a < 3; ++a) {
         vacf_xyz[a] = msd(1, a) - msd(0, a);
         for (int64_t tau = 1; tau < N; ++tau)
@@ -1387,14 +1516,33 @@ struct lpc_batch {
     int64_t *prefix = nullptr;            // count + 3 entries (one list per tile width)
     lpc::FinalizeItem *fin = nullptr;     // count entries
     int64_t *kprefix = nullptr;           // count + 1 entries
+    int64_t *row_counter = nullptr;       // first record row of the chunk a graph replay runs
     hipEvent_t done = nullptr;            // end of the last batch run, awaited by the lattices
+    // Graph of one chunk of steps of the current phase (launches captured once, replayed per
+    // chunk); destroyed when the phase's tables change, after the stream has drained.
+    bool use_graph = true;
+    hipStream_t capture = nullptr;        // stream the graph is recorded on (never run)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int64_t graph_replays = 0;            // chunks run through graphs (for lpc_batch_describe)
+    int64_t direct_steps = 0;             // steps launched one by one
 };
 
 namespace {
 
 struct BatchLayout {
-    size_t items, prefix, fin, kprefix, total;
+    size_t items, prefix, fin, kprefix, counter, total;
 };
+
+void drop_graph(lpc_batch *b)
+{
+    if (b->exec)
+        (void)hipGraphExecDestroy(b->exec);
+    if (b->graph)
+        (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
 
 BatchLayout batch_layout(int32_t count)
 {
@@ -1409,6 +1557,7 @@ BatchLayout batch_layout(int32_t count)
     b.prefix = take(size_t(count + 3) * 8);
     b.fin = take(size_t(count) * sizeof(lpc::FinalizeItem));
     b.kprefix = take(size_t(count + 1) * 8);
+    b.counter = take(8);
     b.total = o;
     return b;
 }
@@ -1462,9 +1611,16 @@ lpc_status lpc_batch_create(lpc_lattice *const *lats, int32_t count, void *arena
     b->prefix = reinterpret_cast<int64_t *>(b->arena + bl.prefix);
     b->fin = reinterpret_cast<lpc::FinalizeItem *>(b->arena + bl.fin);
     b->kprefix = reinterpret_cast<int64_t *>(b->arena + bl.kprefix);
+    b->row_counter = reinterpret_cast<int64_t *>(b->arena + bl.counter);
     if (hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
         delete b;
         return fail(LPC_ERR_DEVICE, "hipEventCreateWithFlags failed");
+    }
+    // default priority, like every stream here
+    if (hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipEventDestroy(b->done);
+        delete b;
+        return fail(LPC_ERR_DEVICE, "hipStreamCreateWithFlags failed");
     }
     *out = b;
     return ok();
@@ -1475,6 +1631,8 @@ lpc_status lpc_batch_destroy(lpc_batch *batch)
     if (!batch)
         return fail(LPC_ERR_ARG, "batch is NULL");
     (void)hipStreamSynchronize(batch->stream);
+    drop_graph(batch);
+    (void)hipStreamDestroy(batch->capture);
     (void)hipEventDestroy(batch->done);
     delete batch;
     return ok();
@@ -1503,6 +1661,18 @@ lpc_status lpc_batch_run(lpc_batch *batch, const int64_t *n_steps)
     // the lattices' own streams may still hold work on them
     for (lpc_lattice *lat : batch->lats)
         LPC_HIP(hipStreamSynchronize(lat->stream));
+    // a lattice that tracks autocorrelation tags and starts from step 0 takes its tagging
+    // step alone (the same kernel and plan as in the batch), then joins the batch
+    std::vector<int64_t> steps_left(n_steps, n_steps + count);
+    for (int32_t l = 0; l < count; ++l) {
+        lpc_lattice *lat = batch->lats[l];
+        if (steps_left[size_t(l)] > 0 && vacf_of(lat->cfg) && lat->steps_done == 0) {
+            if (lpc_status st = queue_steps(lat, 1, batch->stream))
+                return st;
+            --steps_left[size_t(l)];
+        }
+    }
+    n_steps = steps_left.data();
     std::vector<lpc::SweepItem> items;
     std::vector<int64_t> prefix, kprefix;
     std::vector<lpc::FinalizeItem> fin;
@@ -1558,6 +1728,7 @@ lpc_status lpc_batch_run(lpc_batch *batch, const int64_t *n_steps)
             chunk = std::min(chunk, lat->L.chunk);
         }
         LPC_HIP(hipStreamSynchronize(batch->stream));
+        drop_graph(batch);          // the stream has drained: no replay of it is pending
         LPC_HIP(hipMemcpyAsync(batch->items, items.data(), items.size() * sizeof(items[0]),
                                hipMemcpyHostToDevice, batch->stream));
         LPC_HIP(hipMemcpyAsync(batch->prefix, prefix.data(), prefix.size() * 8,
@@ -1568,19 +1739,55 @@ lpc_status lpc_batch_run(lpc_batch *batch, const int64_t *n_steps)
                                hipMemcpyHostToDevice, batch->stream));
         LPC_HIP(hipStreamSynchronize(batch->stream));
         const int64_t total_k = kprefix.back();
-        for (int64_t s0 = 0; s0 < steps; s0 += chunk) {
-            const int64_t c = std::min(chunk, steps - s0);
+        // the launches of one chunk of c steps: c steps of every group, then the records
+        auto enqueue_chunk = [&](hipStream_t st, int64_t s0, int64_t c,
+                                 const int64_t *row_offset) -> lpc_status {
             for (int64_t s = 0; s < c; ++s) {
                 for (const Group &gr : groups) {
                     lpc::StepList list{batch->items + gr.first, batch->prefix + gr.prefix_at,
                                        gr.n, gr.tile_x, gr.total, int32_t((s0 + s) & 1), s};
                     LPC_HIP(lpc::launch_step_list(list, batch->precision,
-                                                  batch->track | gr.variant, batch->maxr,
-                                                  batch->stream));
+                                                  batch->track | gr.variant, batch->maxr, st));
                 }
             }
             LPC_HIP(lpc::launch_finalize_list(batch->fin, batch->kprefix, int32_t(active.size()),
-                                              total_k, c, s0 + 1, batch->stream));
+                                              total_k, c, row_offset ? 0 : s0 + 1, st,
+                                              row_offset));
+            return LPC_OK;
+        };
+        int64_t s0 = 0;
+        // Whole chunks of an even number of steps (the same parities every chunk) replay one
+        // captured graph; its record rows come from a device counter that the graph advances.
+        const int64_t gc = chunk - chunk % 2;
+        if (batch->use_graph && gc >= 2 && steps >= gc) {
+            LPC_HIP(lpc::launch_set_counter(batch->row_counter, 1, 0, batch->stream));
+            LPC_HIP(hipStreamBeginCapture(batch->capture, hipStreamCaptureModeRelaxed));
+            lpc_status st = enqueue_chunk(batch->capture, 0, gc, batch->row_counter);
+            if (st == LPC_OK &&
+                lpc::launch_set_counter(batch->row_counter, 0, gc, batch->capture) != hipSuccess)
+                st = fail(LPC_ERR_DEVICE, "counter launch failed during capture");
+            hipGraph_t g = nullptr;
+            const hipError_t e = hipStreamEndCapture(batch->capture, &g);
+            if (st != LPC_OK) {
+                if (g)
+                    (void)hipGraphDestroy(g);
+                return st;
+            }
+            if (e != hipSuccess)
+                return fail(LPC_ERR_DEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+            batch->graph = g;
+            LPC_HIP(hipGraphInstantiate(&batch->exec, batch->graph, nullptr, nullptr, 0));
+            const int64_t replays = steps / gc;
+            for (int64_t r = 0; r < replays; ++r)
+                LPC_HIP(hipGraphLaunch(batch->exec, batch->stream));
+            batch->graph_replays += replays;
+            s0 = replays * gc;
+        }
+        batch->direct_steps += steps - s0;
+        for (; s0 < steps; s0 += chunk) {
+            const int64_t c = std::min(chunk, steps - s0);
+            if (lpc_status st = enqueue_chunk(batch->stream, s0, c, nullptr))
+                return st;
         }
         for (int32_t l : active) {
             lpc_lattice *lat = batch->lats[l];
@@ -1654,6 +1861,25 @@ lpc_status lpc_spectrum_noalloc(const double *fid, int64_t n_samples, int64_t n_
     // kernel writes all L points of the first buffer, so nothing needs clearing
     LPC_HIP(lpc::launch_fid_spectrum(fid, n_samples, 2, 1, -1, L, work, work + kNoallocFftMax,
                                      spec, static_cast<hipStream_t>(stream)));
+    return ok();
+}
+
+lpc_status lpc_batch_use_graph(lpc_batch *batch, int32_t enable)
+{
+    if (!batch)
+        return fail(LPC_ERR_ARG, "batch is NULL");
+    batch->use_graph = enable != 0;
+    return ok();
+}
+
+lpc_status lpc_batch_describe(const lpc_batch *batch, char *buf, size_t cap)
+{
+    if (!batch || !buf || cap == 0)
+        return fail(LPC_ERR_ARG, "NULL argument");
+    snprintf(buf, cap, "%zu lattices, graphs %s, %lld chunks replayed from graphs, %lld steps "
+                       "launched directly",
+             batch->lats.size(), batch->use_graph ? "on" : "off",
+             (long long)batch->graph_replays, (long long)batch->direct_steps);
     return ok();
 }
 
@@ -1765,10 +1991,34 @@ lpc_status lpc_set_plan(lpc_lattice *lat, int32_t tile_x, int32_t zc)
 {
     if (!lat)
         return fail(LPC_ERR_ARG, "lattice is NULL");
-    if (tile_x != 0 && tile_x != 64 && tile_x != 32 && tile_x != 16 && tile_x != LPC_TILE_LINEAR)
-        return fail(LPC_ERR_ARG, "tile_x = %d is not 0, 1, 64, 32 or 16", tile_x);
+    if (tile_x != 0 && tile_x != 64 && tile_x != 32 && tile_x != 16 && tile_x != LPC_TILE_LINEAR &&
+        tile_x != LPC_TILE_TWO_STEP)
+        return fail(LPC_ERR_ARG, "tile_x = %d is not 0, 1, 2, 64, 32 or 16", tile_x);
     if (zc < 0)
         return fail(LPC_ERR_ARG, "zc = %d is negative", zc);
+    if (tile_x == LPC_TILE_TWO_STEP) {
+        if (!two_step_available(lat->cfg))
+            return fail(LPC_ERR_ARG, "two steps per pass need the plain variant (no mobility "
+                                     "field, no reservoir axis)");
+        if (lpc_status s = use_device(lat))
+            return s;
+        lpc::Geometry g{lat->cfg.n[0], lat->cfg.n[1], lat->cfg.n[2],
+                        {lat->cfg.bc[0], lat->cfg.bc[1], lat->cfg.bc[2]}};
+        lpc::SweepPlan p = lpc::make_plan2(g, lat->occupancy2, lat->cus, zc_floor(lat->cfg));
+        if (zc > 0)
+            p = lpc::with_z_chunk(p, g, zc);
+        if (2 * size_t(p.nblocks) * lat->L.K * 8 > lat->L.partial_bytes)
+            return fail(LPC_ERR_ARG, "plan with %lld workgroups does not fit the partial sums",
+                        (long long)p.nblocks);
+        if (lpc_status s = sync(lat))
+            return s;
+        lat->plan2 = p;
+        lat->chunk2 = two_step_chunk(lat->L, p);
+        lat->steps_per_pass = 2;
+        if (lpc_status s = upload_solo(lat))
+            return s;
+        return ok();
+    }
     const int32_t linear_max = lpc::linear_tile_max_nx(lat->cfg.precision, variant_of(lat->cfg));
     if (tile_x == LPC_TILE_LINEAR && lat->cfg.n[0] > linear_max)
         return fail(LPC_ERR_ARG,
@@ -1791,6 +2041,7 @@ lpc_status lpc_set_plan(lpc_lattice *lat, int32_t tile_x, int32_t zc)
     L.plan = p;
     set_chunk(L);
     lat->L = L;
+    lat->steps_per_pass = 1;
     if (lpc_status s = upload_solo(lat))
         return s;
     return ok();
@@ -1801,11 +2052,19 @@ lpc_status lpc_describe(const lpc_lattice *lat, char *buf, size_t cap)
     if (!lat || !buf || cap == 0)
         return fail(LPC_ERR_ARG, "NULL argument");
     const lpc::SweepPlan &p = lat->L.plan;
-    snprintf(buf, cap,
-             "tile %dx%d, zc %d, grid %dx%dx%d = %lld workgroups, %lld steps per finalize, "
-             "arena %zu bytes",
-             p.tx, p.ty, p.zc, p.gx, p.gy, p.gz, (long long)p.nblocks, (long long)lat->L.chunk,
-             lat->L.total);
+    int n = snprintf(buf, cap,
+                     "tile %dx%d, zc %d, grid %dx%dx%d = %lld workgroups, %lld steps per finalize, "
+                     "arena %zu bytes, steps per pass %d",
+                     p.tx, p.ty, p.zc, p.gx, p.gy, p.gz, (long long)p.nblocks,
+                     (long long)lat->L.chunk, lat->L.total, lat->steps_per_pass);
+    if (lat->steps_per_pass == 2 && n >= 0 && size_t(n) < cap) {
+        const lpc::SweepPlan &q = lat->plan2;
+        snprintf(buf + n, cap - size_t(n),
+                 ", two-step tile %dx%d, zc %d, grid %dx%dx%d = %lld workgroups, %lld steps per "
+                 "finalize",
+                 lpc::kTwoStepTileX, lpc::kTwoStepTileY, q.zc, q.gx, q.gy, q.gz,
+                 (long long)q.nblocks, (long long)lat->chunk2);
+    }
     return ok();
 }
 

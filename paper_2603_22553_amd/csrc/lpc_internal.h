@@ -14,7 +14,12 @@ struct StateView {
     double *rho;
     void *re, *im;
     void *m1[3], *m2[3];
+    void *v[3];        // first-displacement tags per axis (velocity autocorrelation), or null
 };
+
+// Track bit of the velocity autocorrelation field (LPC_TRACK_VACF): with it the moment
+// template parameter of the sweep is 2 (moments and tags) instead of 1.
+constexpr uint32_t kTrackVacf = 4u;
 
 struct Geometry {
     int32_t nx, ny, nz;
@@ -34,10 +39,14 @@ struct SweepPlan {
 
 // SweepPlan.tx of a linear tile.
 constexpr int32_t kTileLinear = 1;
+// SweepPlan.tx of a two-step plan: tiles of 30 x 6 owned columns, each pass two steps
+// (plain variant only).
+constexpr int32_t kTileTwoStep = 2;
+constexpr int32_t kTwoStepTileX = 30, kTwoStepTileY = 6;
 
 // Kernel variant bit carried next to the track bits: the lattice has a mobility field or
 // a reservoir axis, and runs the extended sweep variant.
-constexpr uint32_t kVariantExtended = 4u;
+constexpr uint32_t kVariantExtended = 8u;
 
 // Geometry.bc value of an axis with fixed ghost sites beyond its faces.
 constexpr int32_t kBcReservoir = 2;
@@ -58,13 +67,15 @@ struct StepArgs {
     int32_t K;           // record width
     double p0;
     double fc;             // centre of the accessible free energies (FP64 cell weights)
-    const void *F;
+    const void *F;         // free energies (float path), factors e^{F - fc} (FP64 path)
     const void *theta;
     const uint8_t *region;
     const void *mu;        // per-site mobility (storage type), or null
     const double *ghost;   // 6 faces x (F, rho, Re m, Im m) for reservoir axes
     StateView src, dst;
     double *partials;    // [K][nblocks] for this step
+    int32_t tag;         // 1 on the first step after a start: the autocorrelation tags are set
+    int32_t pad;
 };
 
 // Upper bound on the workgroups of any plan for g (sizes the per-step partial sums).
@@ -82,8 +93,12 @@ SweepPlan make_plan(const Geometry &g, int32_t blocks_per_cu, int32_t cus, int32
 int32_t linear_tile_max_nx(int32_t precision, uint32_t track);
 // The plan with its z-chunk forced to zc planes (zc >= 1).
 SweepPlan with_z_chunk(SweepPlan p, const Geometry &g, int32_t zc);
-// Resident sweep workgroups per compute unit for this precision, track set and regions.
-int sweep_blocks_per_cu(int32_t precision, uint32_t track, int32_t R);
+// Resident sweep workgroups per compute unit for this precision, track set and regions,
+// for the one-step (steps_per_pass 1) or the two-step kernel (2).
+int sweep_blocks_per_cu(int32_t precision, uint32_t track, int32_t R, int32_t steps_per_pass = 1);
+// Plan of the two-step kernel: 30 x 6 owned columns per tile, z-chunks as make_plan chooses
+// them (at least zc_floor planes).
+SweepPlan make_plan2(const Geometry &g, int32_t blocks_per_cu, int32_t cus, int32_t zc_floor);
 
 // One entry of a sweep work list: a lattice's step arguments (views of the parity-0 step)
 // and its plan.
@@ -120,7 +135,10 @@ struct FinalizeItem {
 hipError_t launch_step_list(const StepList &list, int32_t precision, uint32_t track, int32_t maxr,
                             hipStream_t s);
 hipError_t launch_finalize_list(const FinalizeItem *items, const int64_t *kprefix, int32_t n_items,
-                                int64_t total_k, int64_t steps, int64_t first_row, hipStream_t s);
+                                int64_t total_k, int64_t steps, int64_t first_row, hipStream_t s,
+                                const int64_t *row_offset = nullptr);
+// *counter = value (add == 0) or *counter += add, on the device in stream order.
+hipError_t launch_set_counter(int64_t *counter, int64_t value, int64_t add, hipStream_t s);
 hipError_t launch_record(const SweepPlan &plan, const StepArgs &a, hipStream_t s);
 hipError_t launch_finalize(const double *partials, int64_t nblocks, int32_t K, int64_t steps,
                            double *records_out, hipStream_t s);
@@ -137,6 +155,10 @@ hipError_t launch_fill_field(int32_t precision, void *dst, int64_t n, double val
 // Boltzmann weights w_i = exp(-(F_i - Fmin)) into w, block sums into partials[nb].
 hipError_t launch_boltzmann_weights(int32_t precision, const void *F, double Fmin, double *w,
                                     int64_t n, double *partials, int64_t *nb, hipStream_t s);
+// E_i = exp(F_i - fc), FP64: the per-site Boltzmann factors the FP64 sweep reads in place of
+// the free energies.
+hipError_t launch_boltzmann_factors(const double *F, double *E, int64_t n, double fc,
+                                    hipStream_t s);
 // rho_i = w_i * scale_num / (*Z) in place.
 hipError_t launch_boltzmann_scale(double *w, int64_t n, double numer, const double *Z,
                                   hipStream_t s);

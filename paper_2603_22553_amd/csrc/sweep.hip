@@ -65,6 +65,7 @@ struct View {
     double *rho;
     S *re, *im;
     S *m1[3], *m2[3];
+    S *v[3];
 };
 
 template <typename S>
@@ -77,6 +78,7 @@ __host__ __device__ inline View<S> typed(const StateView &v)
     for (int a = 0; a < 3; ++a) {
         t.m1[a] = static_cast<S *>(v.m1[a]);
         t.m2[a] = static_cast<S *>(v.m2[a]);
+        t.v[a] = static_cast<S *>(v.v[a]);
     }
     return t;
 }
@@ -117,7 +119,7 @@ __device__ inline double exact_flux(double p_in, double xj, double p_out, double
 // Register accumulators of one thread's record contributions.
 template <int MAXR>
 struct RecAcc {
-    double re[MAXR], im[MAXR], u[MAXR], s1[3], s2[3];
+    double re[MAXR], im[MAXR], u[MAXR], s1[3], s2[3], c[3];
 
     __device__ void zero()
     {
@@ -126,7 +128,7 @@ struct RecAcc {
             re[r] = im[r] = u[r] = 0.0;
 #pragma unroll
         for (int a = 0; a < 3; ++a)
-            s1[a] = s2[a] = 0.0;
+            s1[a] = s2[a] = c[a] = 0.0;
     }
 
     __device__ void add_site(int r, double vre, double vim, double vu)
@@ -155,9 +157,16 @@ __device__ inline double wave_sum(double v)
     return v;
 }
 
+// Record entries per region and after the regions: K = 3 R + 6, plus 3 with the velocity
+// autocorrelation (moment template parameter 2).
+__host__ __device__ constexpr int record_slots(int R, int MSD)
+{
+    return 3 * R + 6 + (MSD == 2 ? 3 : 0);
+}
+
 // Reduces the block's accumulators into partials[k * nblocks + blk], k < K, in a fixed
 // order (butterfly inside each wave, then waves in index order).
-template <int MAXR, int NWAVES>
+template <int MAXR, int NWAVES, bool VAC = false>
 __device__ void block_reduce(RecAcc<MAXR> &acc, int R, int K, double *partials, int64_t nblocks,
                              int64_t blk, double *lds)
 {
@@ -180,6 +189,11 @@ __device__ void block_reduce(RecAcc<MAXR> &acc, int R, int K, double *partials, 
     for (int a = 0; a < 3; ++a) {
         push(acc.s1[a], 3 * R + a);
         push(acc.s2[a], 3 * R + 3 + a);
+    }
+    if (VAC) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            push(acc.c[a], 3 * R + 6 + a);
     }
     __syncthreads();
     if (tid < K) {
@@ -204,13 +218,14 @@ __device__ inline int64_t logical_block(int64_t b, int64_t padded)
 // Values of one site that its neighbours read: population, free energy, magnetisation,
 // displacement moments and (extended variant) mobility, in the storage type S (rho is
 // always double).
-template <typename S, bool FID, bool MSD, bool EXT>
+template <typename S, bool FID, int MSD, bool EXT>
 struct Cell {
     double rho;
     S F;      // FP64 path: free energy when loaded, then E = e^{F - c} once weighed
     S G;      // FP64 path: G = e^{c - F} once weighed
     S re, im;
     S m1[3], m2[3];
+    S v[3];   // first-displacement tags (moment parameter 2)
     S mu;
 };
 
@@ -225,16 +240,21 @@ struct PerCellWeights<double> {
     static constexpr bool on = true;
 };
 
-// FP64 path: replaces the loaded free energy by E = e^{F - c} and adds G = 1/E = e^{c - F}.
-// An inaccessible site (sentinel F) gets E = inf, G = 0, hence zero acceptance towards it.
-template <typename S, bool FID, bool MSD, bool EXT>
-__device__ inline void weigh(Cell<S, FID, MSD, EXT> &c, double fc)
+// Boltzmann factor E = e^{F - c} of a free energy on the FP64 path (c centres the accessible
+// range). The sweep reads a field of these factors, set once per free-energy field by
+// k_boltzmann_factors, instead of the free energies.
+__device__ inline double boltzmann_factor(double F, double fc)
 {
-    if (PerCellWeights<S>::on) {
-        const double e = exp(static_cast<double>(c.F) - fc);
-        c.F = static_cast<S>(e);
-        c.G = static_cast<S>(1.0 / e);
-    }
+    return exp(F - fc);
+}
+
+// FP64 path: adds G = 1/E = e^{c - F} to a cell loaded with its factor E. An inaccessible site
+// (sentinel F) has E = inf, so G = 0: zero acceptance towards it.
+template <typename S, bool FID, int MSD, bool EXT>
+__device__ inline void weigh(Cell<S, FID, MSD, EXT> &c, double)
+{
+    if (PerCellWeights<S>::on)
+        c.G = static_cast<S>(1.0 / static_cast<double>(c.F));
 }
 
 // Byte offsets of one column (or halo column) in the 8-byte, S-sized and 1-byte arrays.
@@ -243,7 +263,7 @@ struct Off {
 };
 
 // Loads the values of a site that its neighbours read.
-template <typename S, bool FID, bool MSD, bool EXT>
+template <typename S, bool FID, int MSD, bool EXT>
 __device__ inline void load_cell(Cell<S, FID, MSD, EXT> &c, const View<S> &v, const S *F,
                                  const S *MU, int64_t pz, Off o)
 {
@@ -262,16 +282,22 @@ __device__ inline void load_cell(Cell<S, FID, MSD, EXT> &c, const View<S> &v, co
             c.m2[b] = ld(v.m2[b] + pz, o.bs);
         }
     }
+    if (MSD == 2) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            c.v[b] = ld(v.v[b] + pz, o.bs);
+    }
 }
 
 // The fixed ghost site beyond reservoir face `face` (2 * axis + side): free energy,
 // population and magnetisation from the table, zero moments, mobility 1; weighed.
-template <typename S, bool FID, bool MSD, bool EXT>
+template <typename S, bool FID, int MSD, bool EXT>
 __device__ inline void ghost_cell(Cell<S, FID, MSD, EXT> &c, const double *ghost, int face,
                                   double fc)
 {
     const double *v = ghost + 4 * face;
-    c.F = static_cast<S>(v[0]);
+    c.F = PerCellWeights<S>::on ? static_cast<S>(boltzmann_factor(v[0], fc))
+                                : static_cast<S>(v[0]);
     weigh(c, fc);
     c.rho = v[1];
     if (FID) {
@@ -281,7 +307,7 @@ __device__ inline void ghost_cell(Cell<S, FID, MSD, EXT> &c, const double *ghost
     if (MSD) {
 #pragma unroll
         for (int b = 0; b < 3; ++b)
-            c.m1[b] = c.m2[b] = S(0);
+            c.m1[b] = c.m2[b] = c.v[b] = S(0);   // a ghost holds no tagged particle
     }
     if (EXT)
         c.mu = S(1);
@@ -292,7 +318,8 @@ __device__ inline void ghost_cell(Cell<S, FID, MSD, EXT> &c, const double *ghost
 template <typename S>
 struct Acc {
     double rho, pout;
-    S re, im, m1[3], m2[3];
+    S re, im, m1[3], m2[3], v[3];
+    double mv[3], ms[3];   // mean displacement and mean square of the site's next move
 };
 
 __device__ inline float fast_exp(float v)
@@ -324,9 +351,20 @@ __device__ inline void link_pair_weighed(double Ei, double Gi, double Ej, double
 
 // Gathers the fields arriving over one link from neighbour `nb`, which lies one hop along
 // axis AX with sign SGN; the arriving move nb -> i has hop component d = -SGN.
-template <int AX, int SGN, typename S, bool FID, bool MSD, bool EXT>
-__device__ inline void gather(const Cell<S, FID, MSD, EXT> &nb, S p_in, Acc<S> &f)
+template <int AX, int SGN, typename S, bool FID, int MSD, bool EXT>
+__device__ inline void gather(const Cell<S, FID, MSD, EXT> &nb, S p_in, Acc<S> &f, bool tag)
 {
+    if (MSD == 2) {
+        // the tags: each particle's first displacement, set on the first step (the tags
+        // before it are zero), then carried like a population
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            S x = nb.v[b];
+            if (b == AX && tag)
+                x = SGN > 0 ? x - static_cast<S>(nb.rho) : x + static_cast<S>(nb.rho);
+            f.v[b] = fma(p_in, x, f.v[b]);
+        }
+    }
     if (FID) {
         f.re = fma(p_in, nb.re, f.re);
         f.im = fma(p_in, nb.im, f.im);
@@ -353,33 +391,44 @@ __device__ inline void gather(const Cell<S, FID, MSD, EXT> &nb, S p_in, Acc<S> &
 // Attempt probability of the link: p0, scaled in the extended variant by the smaller
 // mobility of its two ends (the same value at both ends; exactly p0 without a mobility
 // field).
-template <typename S, bool FID, bool MSD, bool EXT>
+template <typename S, bool FID, int MSD, bool EXT>
 __device__ inline S link_p0(const Cell<S, FID, MSD, EXT> &c, const Cell<S, FID, MSD, EXT> &nb,
                             S p0)
 {
     return EXT ? p0 * fmin(c.mu, nb.mu) : p0;
 }
 
-template <int AX, int SGN, bool FID, bool MSD, bool EXT>
+template <int AX, int SGN, bool FID, int MSD, bool EXT>
 __device__ inline void add_link(const Cell<double, FID, MSD, EXT> &c,
-                                const Cell<double, FID, MSD, EXT> &nb, double p0, Acc<double> &f)
+                                const Cell<double, FID, MSD, EXT> &nb, double p0, Acc<double> &f,
+                                bool tag)
 {
     double p_out, p_in;
     link_pair_weighed(c.F, c.G, nb.F, nb.G, link_p0(c, nb, p0), p_out, p_in);
     f.rho += exact_flux(p_in, nb.rho, p_out, c.rho);
     f.pout += p_out;
-    gather<AX, SGN>(nb, p_in, f);
+    if (MSD == 2) {
+        f.mv[AX] += SGN > 0 ? p_out : -p_out;
+        f.ms[AX] += p_out;
+    }
+    gather<AX, SGN>(nb, p_in, f, tag);
 }
 
-template <int AX, int SGN, bool FID, bool MSD, bool EXT>
+template <int AX, int SGN, bool FID, int MSD, bool EXT>
 __device__ inline void add_link(const Cell<float, FID, MSD, EXT> &c,
-                                const Cell<float, FID, MSD, EXT> &nb, float p0, Acc<float> &f)
+                                const Cell<float, FID, MSD, EXT> &nb, float p0, Acc<float> &f,
+                                bool tag)
 {
     float p_out, p_in;
     link_pair(c.F, nb.F, link_p0(c, nb, p0), p_out, p_in);
     f.rho = fma(static_cast<double>(p_in), nb.rho, f.rho);
     f.pout += static_cast<double>(p_out);
-    gather<AX, SGN>(nb, p_in, f);
+    if (MSD == 2) {
+        const double q = static_cast<double>(p_out);
+        f.mv[AX] += SGN > 0 ? q : -q;
+        f.ms[AX] += q;
+    }
+    gather<AX, SGN>(nb, p_in, f, tag);
 }
 
 // stay * x + gathered, finished in double for float storage (one rounding to float).
@@ -465,49 +514,98 @@ __device__ inline void rotation(float t, float &sn, float &cm1)
     cm1 = c;
 }
 
-// New state of a site from its old values and gather sums; stores it and adds its record
-// contributions.
-template <typename S, bool FID, bool MSD, bool EXT, int MAXR>
-__device__ inline void finish_site(const Cell<S, FID, MSD, EXT> &c, const Acc<S> &f, S theta, int r,
-                                   const View<S> &dst, int64_t pz, Off o, RecAcc<MAXR> &acc)
+// New state of a site from its old values and gather sums, into n (its fields F, G and mu
+// are carried over): one step of Eqs. (1), (13) and the moment recursion.
+template <typename S, bool FID, int MSD, bool EXT>
+__device__ inline void advance_site(const Cell<S, FID, MSD, EXT> &c, const Acc<S> &f, S theta,
+                                    Cell<S, FID, MSD, EXT> &n)
 {
     const double stay = 1.0 - f.pout;
-    const double rho_n = new_rho(stay, c.rho, f);
-    st(dst.rho + pz, o.b8, rho_n);
-    double out_re = 0.0, out_im = 0.0;
+    n.rho = new_rho(stay, c.rho, f);
+    n.F = c.F;
+    if (PerCellWeights<S>::on)
+        n.G = c.G;
+    if (EXT)
+        n.mu = c.mu;
     if (FID) {
         const S gre = stay_update(stay, c.re, f.re), gim = stay_update(stay, c.im, f.im);
         S sn, cm1;                                            // sin t, cos t - 1
         rotation(theta, sn, cm1);
-        const S nre = gre + (gre * cm1 - gim * sn);
-        const S nim = gim + (gim * cm1 + gre * sn);
-        st(dst.re + pz, o.bs, nre);
-        st(dst.im + pz, o.bs, nim);
-        out_re = static_cast<double>(nre);
-        out_im = static_cast<double>(nim);
+        n.re = gre + (gre * cm1 - gim * sn);
+        n.im = gim + (gim * cm1 + gre * sn);
     }
     if (MSD) {
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-            const S v1 = stay_update(stay, c.m1[b], f.m1[b]);
-            const S v2 = stay_update(stay, c.m2[b], f.m2[b]);
-            st(dst.m1[b] + pz, o.bs, v1);
-            st(dst.m2[b] + pz, o.bs, v2);
-            acc.s1[b] += static_cast<double>(v1);
-            acc.s2[b] += static_cast<double>(v2);
+            n.m1[b] = stay_update(stay, c.m1[b], f.m1[b]);
+            n.m2[b] = stay_update(stay, c.m2[b], f.m2[b]);
         }
     }
-    acc.add_site(r, out_re, out_im, rho_n);
+    if (MSD == 2) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            n.v[b] = stay_update(stay, c.v[b], f.v[b]);
+    }
+}
+
+// Record contributions of a site's new values (region r).
+template <typename S, bool FID, int MSD, bool EXT, int MAXR>
+__device__ inline void record_cell(const Cell<S, FID, MSD, EXT> &n, int r, RecAcc<MAXR> &acc)
+{
+    if (MSD) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            acc.s1[b] += static_cast<double>(n.m1[b]);
+            acc.s2[b] += static_cast<double>(n.m2[b]);
+        }
+    }
+    acc.add_site(r, FID ? static_cast<double>(n.re) : 0.0, FID ? static_cast<double>(n.im) : 0.0,
+                 n.rho);
+}
+
+// New state of a site from its old values and gather sums; stores it and adds its record
+// contributions.
+template <typename S, bool FID, int MSD, bool EXT, int MAXR>
+__device__ inline void finish_site(const Cell<S, FID, MSD, EXT> &c, const Acc<S> &f, S theta, int r,
+                                   const View<S> &dst, int64_t pz, Off o, RecAcc<MAXR> &acc,
+                                   bool tag = false)
+{
+    Cell<S, FID, MSD, EXT> n;
+    advance_site(c, f, theta, n);
+    if (MSD == 2) {
+        // Eq. (4): the tagged particles at the site make their next move with mean
+        // displacement mv, so sum_i V_i mv_i is <dx_1 dx_{1+tau}> of the state's lag tau; on
+        // the tagging step (no tags yet) the entry is the mean square of one step, C(0)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            acc.c[b] += tag ? c.rho * f.ms[b] : static_cast<double>(c.v[b]) * f.mv[b];
+            st(dst.v[b] + pz, o.bs, n.v[b]);
+        }
+    }
+    st(dst.rho + pz, o.b8, n.rho);
+    if (FID) {
+        st(dst.re + pz, o.bs, n.re);
+        st(dst.im + pz, o.bs, n.im);
+    }
+    if (MSD) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            st(dst.m1[b] + pz, o.bs, n.m1[b]);
+            st(dst.m2[b] + pz, o.bs, n.m2[b]);
+        }
+    }
+    record_cell<S, FID, MSD, EXT, MAXR>(n, r, acc);
 }
 
 // LDS image of one z-plane of a tile with a one-site halo in x and y, one array per field.
-template <typename S, bool FID, bool MSD, bool EXT, int NL>
+template <typename S, bool FID, int MSD, bool EXT, int NL>
 struct TileLds {
     double rho[NL];
     S F[NL];
     S G[PerCellWeights<S>::on ? NL : 1];
     S re[FID ? NL : 1], im[FID ? NL : 1];
     S m1[3][MSD ? NL : 1], m2[3][MSD ? NL : 1];
+    S v[3][MSD == 2 ? NL : 1];
     S mu[EXT ? NL : 1];
 
     template <typename C>
@@ -529,6 +627,11 @@ struct TileLds {
                 m1[b][s] = c.m1[b];
                 m2[b][s] = c.m2[b];
             }
+        }
+        if (MSD == 2) {
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                v[b][s] = c.v[b];
         }
     }
 
@@ -552,6 +655,11 @@ struct TileLds {
                 c.m2[b] = m2[b][s];
             }
         }
+        if (MSD == 2) {
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                c.v[b] = v[b][s];
+        }
     }
 };
 
@@ -571,7 +679,7 @@ constexpr int64_t kLdsShare = 80 * 1024 - 1024;
 
 // Widest x extent run on linear tiles: their double-buffered LDS window of 256 + 2 nx cells
 // must fit the share (and one halo site per thread needs 2 nx <= 256).
-template <typename S, bool FID, bool MSD>
+template <typename S, bool FID, int MSD>
 constexpr int linear_nx_max()
 {
     constexpr int64_t cell = int64_t(sizeof(TileLds<S, FID, MSD, false, 2>)) -
@@ -595,12 +703,13 @@ struct TileThread {
     int li, hslot, hghost;   // hghost: reservoir face whose ghost fills the halo slot, or -1
     int oxm, oxp, oy;        // LDS offsets of the x-1, x+1 and (+-) y neighbours from li
     bool act, has_xm, has_xp, has_ym, has_yp;
+    uint32_t ghosts;         // bits 0..3: the x-1, x+1, y-1, y+1 neighbour is a reservoir ghost
 };
 
 // One z-plane of the tile: stage it in LDS buffer `L` (own site + halo site), prefetch
 // plane z+2 (own column) into `nx2` and the halo of plane z+1 into `halo`, wait for the
 // whole tile, then update every site of the plane from LDS (x, y) and registers (z).
-template <typename S, bool FID, bool MSD, bool EXT, int MAXR, int TX, typename LDS>
+template <typename S, bool FID, int MSD, bool EXT, int MAXR, int TX, typename LDS>
 __device__ __forceinline__ void plane_step(LDS &L, const StepArgs &a, const TileThread &th,
                                            const View<S> &src, const View<S> &dst, const S *F,
                                            const S *MU, const S *TH, int64_t plane, int z,
@@ -638,45 +747,48 @@ __device__ __forceinline__ void plane_step(LDS &L, const StepArgs &a, const Tile
     if (!th.act)
         return;
     const S p0 = static_cast<S>(a.p0);
+    const bool tag = MSD == 2 && a.tag;
     weigh(nxt, a.fc);                   // first use of the plane above (prefetched earlier)
     Acc<S> f{};
     Cell<S, FID, MSD, EXT> nb;
+    // particles that come in from a reservoir ghost were not in the lattice at the start:
+    // they carry no autocorrelation tag
     if (th.has_xm) {
         L.get(th.li + th.oxm, nb);
-        add_link<0, -1>(cur, nb, p0, f);
+        add_link<0, -1>(cur, nb, p0, f, tag && !(th.ghosts & 1u));
     }
     if (th.has_xp) {
         L.get(th.li + th.oxp, nb);
-        add_link<0, +1>(cur, nb, p0, f);
+        add_link<0, +1>(cur, nb, p0, f, tag && !(th.ghosts & 2u));
     }
     if (th.has_ym) {
         L.get(th.li - th.oy, nb);
-        add_link<1, -1>(cur, nb, p0, f);
+        add_link<1, -1>(cur, nb, p0, f, tag && !(th.ghosts & 4u));
     }
     if (th.has_yp) {
         L.get(th.li + th.oy, nb);
-        add_link<1, +1>(cur, nb, p0, f);
+        add_link<1, +1>(cur, nb, p0, f, tag && !(th.ghosts & 8u));
     }
     // the z ghost cells are built where they are used: filling window registers with them
     // inside the plane loop costs the whole loop registers
     if (z > 0 || zper) {
-        add_link<2, -1>(cur, prv, p0, f);
+        add_link<2, -1>(cur, prv, p0, f, tag);
     } else if (zres) {
         Cell<S, FID, MSD, EXT> gz;
         ghost_cell(gz, a.ghost, 4, a.fc);
-        add_link<2, -1>(cur, gz, p0, f);
+        add_link<2, -1>(cur, gz, p0, f, false);
     }
     if (z + 1 < g.nz || zper) {
-        add_link<2, +1>(cur, nxt, p0, f);
+        add_link<2, +1>(cur, nxt, p0, f, tag);
     } else if (zres) {
         Cell<S, FID, MSD, EXT> gz;
         ghost_cell(gz, a.ghost, 5, a.fc);
-        add_link<2, +1>(cur, gz, p0, f);
+        add_link<2, +1>(cur, gz, p0, f, false);
     }
     const int64_t pz = plane * z;
     const S theta = FID ? ld(TH + pz, own.bs) : S(0);
     const int r = MAXR == 1 ? 0 : ld(a.region + pz, own.b1);
-    finish_site<S, FID, MSD, EXT, MAXR>(cur, f, theta, r, dst, pz, own, acc);
+    finish_site<S, FID, MSD, EXT, MAXR>(cur, f, theta, r, dst, pz, own, acc, tag);
 }
 
 // At least two resident workgroups per compute unit (two waves per SIMD): every variant
@@ -688,7 +800,7 @@ __device__ __forceinline__ void plane_step(LDS &L, const StepArgs &a, const Tile
 
 // Tile geometry of the sweep: TY rows of TX columns with a one-site halo, or a linear tile
 // of 256 sites with a window of one row on either side (NL cells in LDS).
-template <typename S, bool FID, bool MSD, bool EXT, int TX>
+template <typename S, bool FID, int MSD, bool EXT, int TX>
 struct TileShape {
     static constexpr bool linear = TX == kTileLinear;
     static constexpr int TY = linear ? kThreads : kThreads / TX;
@@ -721,6 +833,7 @@ __device__ inline void linear_thread(TileThread &th, const Geometry &g, int bx, 
     th.has_xp = x + 1 < nx || xper;
     th.has_ym = y > 0 || yper;
     th.has_yp = y + 1 < g.ny || yper;
+    th.ghosts = 0u;
     const uint32_t col = th.act ? static_cast<uint32_t>(s) : 0u;
     th.own = {col * 8u, col * storage, col};
     th.li = nx + t;
@@ -765,6 +878,8 @@ __device__ inline void block_thread(TileThread &th, const Geometry &g, int bx, i
     th.has_xp = x + 1 < g.nx || xper || xres;
     th.has_ym = y > 0 || yper || yres;
     th.has_yp = y + 1 < g.ny || yper || yres;
+    th.ghosts = (x == 0 && xres ? 1u : 0u) | (x + 1 == g.nx && xres ? 2u : 0u) |
+                (y == 0 && yres ? 4u : 0u) | (y + 1 == g.ny && yres ? 8u : 0u);
     const uint32_t col = th.act ? static_cast<uint32_t>(x + g.nx * y) : 0u;
     th.own = {col * 8u, col * storage, col};
     th.li = (ty + 1) * COLS + tx + 1;
@@ -825,14 +940,14 @@ __device__ inline void block_thread(TileThread &th, const Geometry &g, int bx, i
 // 32-bit byte offsets of its column. Beyond a reservoir face in x or y the halo slot holds
 // the face's ghost cell, set once and never reloaded; in z the ghost cell is built at the
 // first or last plane where its link is added.
-template <typename S, bool FID, bool MSD, bool EXT, int MAXR, int TX>
+template <typename S, bool FID, int MSD, bool EXT, int MAXR, int TX>
 __device__ __forceinline__ void sweep_tile(const StepArgs &a, const SweepPlan &p, int64_t blk)
 {
     using Shape = TileShape<S, FID, MSD, EXT, TX>;
     constexpr int NL = Shape::NL;
     using C = Cell<S, FID, MSD, EXT>;
     __shared__ TileLds<S, FID, MSD, EXT, NL> L0, L1;
-    __shared__ double red[(kThreads / kWave) * (3 * MAXR + 6)];
+    __shared__ double red[(kThreads / kWave) * record_slots(MAXR, MSD)];
     const Geometry &g = a.g;
     int bx, by, bz;
     tile_coords(p, blk, bx, by, bz);
@@ -890,14 +1005,14 @@ __device__ __forceinline__ void sweep_tile(const StepArgs &a, const SweepPlan &p
                                                     w0, w1, w2, halo, acc);
     }
     __syncthreads();
-    block_reduce<MAXR, kThreads / kWave>(acc, a.R, a.K, a.partials, p.nblocks, blk, red);
+    block_reduce<MAXR, kThreads / kWave, MSD == 2>(acc, a.R, a.K, a.partials, p.nblocks, blk, red);
 }
 
 // One step of every lattice in a work list: workgroup w (after the XCD renumbering) runs
 // tile w - prefix[l] of item l, prefix[l] <= w < prefix[l + 1]. The items hold the views
 // of the step with parity 0; parity 1 swaps source and destination. Each lattice keeps its
 // own plan, so a lattice gives the same bits alone (a list of one) and in any batch.
-template <typename S, bool FID, bool MSD, bool EXT, int MAXR, int TX>
+template <typename S, bool FID, int MSD, bool EXT, int MAXR, int TX>
 __global__ __launch_bounds__(kThreads, LPC_MIN_WAVES) void k_sweep_tile(
     const SweepItem *__restrict__ items, const int64_t *__restrict__ prefix, int32_t n_items,
     int64_t total, int64_t padded, int32_t parity, int64_t slot)
@@ -924,7 +1039,275 @@ __global__ __launch_bounds__(kThreads, LPC_MIN_WAVES) void k_sweep_tile(
     sweep_tile<S, FID, MSD, EXT, MAXR, TX>(a, p, w - prefix[lo]);
 }
 
-template <typename S, bool FID, bool MSD, int MAXR>
+// ---------------------------------------------------------------------------- two steps per pass
+
+// Temporal blocking: one pass advances a lattice by two steps, reading the state and the
+// fields once and writing the state once. The 256 threads of a workgroup cover a 32 x 8
+// block of x-y columns (the A columns) and take the first step on them; the inner 30 x 6
+// columns are the tile the workgroup owns, and it takes the second step there from the
+// first step's values of the A columns, which never leave the chip. The first step on the
+// ring of A columns around the tile repeats work of the neighbouring tiles. z is marched as
+// in the one-step sweep, with the first step one plane ahead of the second: the first step
+// reads x-y neighbours from a double-buffered LDS image of the level-0 plane with a halo of
+// one more site (34 x 10), the second from a double-buffered image of the level-1 plane
+// (32 x 8); each thread keeps the z-window of its column at both levels in registers. Per
+// site the arithmetic is that of the one-step sweep, so the state after the pass is bit for
+// bit that of two one-step sweeps; the per-step sums run over other tiles.
+constexpr int kTwoAX = 32, kTwoAY = 8;                      // A columns of a tile
+constexpr int kTwoOX = kTwoAX - 2, kTwoOY = kTwoAY - 2;     // owned columns
+constexpr int kTwoL0X = kTwoAX + 2, kTwoL0Y = kTwoAY + 2;   // level-0 image with its halo
+constexpr int kTwoHalo = 2 * kTwoL0X + 2 * kTwoAY;          // halo cells of that image
+static_assert(kTwoAX * kTwoAY == kThreads, "one A column per thread");
+static_assert(kTwoHalo <= kThreads, "one halo cell per thread");
+static_assert(kTwoOX == kTwoStepTileX && kTwoOY == kTwoStepTileY, "two-step tile of the plans");
+
+// v on an axis of n sites: itself inside, wrapped on a periodic axis, -1 beyond a closed
+// face.
+__device__ inline int wrap_axis(int v, int n, bool periodic)
+{
+    if (v >= 0 && v < n)
+        return v;
+    if (!periodic)
+        return -1;
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// Per-thread constants of a two-step tile: the thread's A column (its slots in both LDS
+// images, whether it exists and whether the tile owns it), the existence of its x and y
+// neighbours, and the level-0 halo cell the thread loads.
+struct TwoThread {
+    Off own, halo;
+    int l0, l1, hslot;
+    bool act, owned, has_xm, has_xp, has_ym, has_yp;
+};
+
+__device__ inline void two_thread(TwoThread &th, const Geometry &g, int bx, int by, int t,
+                                  uint32_t storage)
+{
+    const bool xper = g.bc[0] == 0, yper = g.bc[1] == 0;
+    const int tx = t % kTwoAX, ty = t / kTwoAX;
+    const int x0 = bx * kTwoOX, y0 = by * kTwoOY;       // the first owned column
+    const int ax = x0 - 1 + tx, ay = y0 - 1 + ty;       // the A column, before wrapping
+    const int px = wrap_axis(ax, g.nx, xper), py = wrap_axis(ay, g.ny, yper);
+    th.act = px >= 0 && py >= 0;
+    th.owned = tx >= 1 && tx <= kTwoOX && ty >= 1 && ty <= kTwoOY && ax < g.nx && ay < g.ny;
+    th.has_xm = th.act && (xper || px > 0);
+    th.has_xp = th.act && (xper || px + 1 < g.nx);
+    th.has_ym = th.act && (yper || py > 0);
+    th.has_yp = th.act && (yper || py + 1 < g.ny);
+    const uint32_t col = th.act ? static_cast<uint32_t>(px + g.nx * py) : 0u;
+    th.own = {col * 8u, col * storage, col};
+    th.l0 = (ty + 1) * kTwoL0X + tx + 1;
+    th.l1 = ty * kTwoAX + tx;
+    th.hslot = -1;
+    uint32_t hcol = 0u;
+    if (t < kTwoHalo) {
+        int i, j;                                       // cell (i, j) of the 34 x 10 image
+        if (t < kTwoL0X) {
+            i = t;
+            j = 0;
+        } else if (t < 2 * kTwoL0X) {
+            i = t - kTwoL0X;
+            j = kTwoL0Y - 1;
+        } else if (t < 2 * kTwoL0X + kTwoAY) {
+            i = 0;
+            j = t - 2 * kTwoL0X + 1;
+        } else {
+            i = kTwoL0X - 1;
+            j = t - 2 * kTwoL0X - kTwoAY + 1;
+        }
+        const bool corner = (i == 0 || i == kTwoL0X - 1) && (j == 0 || j == kTwoL0Y - 1);
+        const int hx = wrap_axis(x0 - 2 + i, g.nx, xper), hy = wrap_axis(y0 - 2 + j, g.ny, yper);
+        if (!corner && hx >= 0 && hy >= 0) {              // corners are nobody's neighbour
+            th.hslot = j * kTwoL0X + i;
+            hcol = static_cast<uint32_t>(hx + g.nx * hy);
+        }
+    }
+    th.halo = {hcol * 8u, hcol * storage, hcol};
+}
+
+// Gather sums of one site from its x and y neighbours in an LDS image `w` cells wide and its
+// z neighbours in registers (each only where it exists).
+template <typename S, bool FID, int MSD, typename LDS>
+__device__ inline void gather_site(const LDS &L, int slot, int w, const TwoThread &th,
+                                   const Cell<S, FID, MSD, false> &cur,
+                                   const Cell<S, FID, MSD, false> &below, bool zm,
+                                   const Cell<S, FID, MSD, false> &above, bool zp, S p0,
+                                   Acc<S> &f)
+{
+    Cell<S, FID, MSD, false> nb;
+    if (th.has_xm) {
+        L.get(slot - 1, nb);
+        add_link<0, -1>(cur, nb, p0, f, false);
+    }
+    if (th.has_xp) {
+        L.get(slot + 1, nb);
+        add_link<0, +1>(cur, nb, p0, f, false);
+    }
+    if (th.has_ym) {
+        L.get(slot - w, nb);
+        add_link<1, -1>(cur, nb, p0, f, false);
+    }
+    if (th.has_yp) {
+        L.get(slot + w, nb);
+        add_link<1, +1>(cur, nb, p0, f, false);
+    }
+    if (zm)
+        add_link<2, -1>(cur, below, p0, f, false);
+    if (zp)
+        add_link<2, +1>(cur, above, p0, f, false);
+}
+
+template <typename S, bool FID, int MSD, int MAXR>
+__device__ __forceinline__ void sweep2_tile(const StepArgs &a, const SweepPlan &p, int64_t blk,
+                                            double *part1, double *part2)
+{
+    using C = Cell<S, FID, MSD, false>;
+    __shared__ TileLds<S, FID, MSD, false, kTwoL0X * kTwoL0Y> LA[2];   // level 0, first step
+    __shared__ TileLds<S, FID, MSD, false, kTwoAX * kTwoAY> LB[2];     // level 1, second step
+    __shared__ double red[(kThreads / kWave) * (3 * MAXR + 6)];
+    const Geometry &g = a.g;
+    int bx, by, bz;
+    tile_coords(p, blk, bx, by, bz);
+    TwoThread th;
+    two_thread(th, g, bx, by, static_cast<int>(threadIdx.x), static_cast<uint32_t>(sizeof(S)));
+    const bool zper = g.bc[2] == 0;
+    const S *F = static_cast<const S *>(a.F);
+    const S *TH = static_cast<const S *>(a.theta);
+    const View<S> src = typed<S>(a.src);
+    const View<S> dst = typed<S>(a.dst);
+    const S p0 = static_cast<S>(a.p0);
+    const int64_t plane = static_cast<int64_t>(g.nx) * g.ny;
+    // owned planes [z0, z1); the first step runs on [za_lo, za_hi] (one more plane on each
+    // side where one exists), the second on [z0, z1)
+    const int z0 = bz * p.zc, z1 = min(g.nz, z0 + p.zc);
+    const int za_lo = z0 > 0 || zper ? z0 - 1 : z0;
+    const int za_hi = z1 < g.nz || zper ? z1 : z1 - 1;
+    auto pz_of = [&](int z) { return wrap_axis(z, g.nz, zper); };
+    C w_prv, w_cur, w_nxt, w_fly, halo;   // level 0 of the own column at za - 1 .. za + 2
+    C v_prv, v_cur, c1;                   // level 1 at zb - 1, zb and za (zb = za - 1)
+    S th_cur = S(0), th_nxt = S(0);       // phases at zb and za
+    int r_cur = 0, r_nxt = 0;             // regions at zb and za
+    RecAcc<MAXR> acc1, acc2;
+    acc1.zero();
+    acc2.zero();
+    if (th.act) {
+        int q = pz_of(za_lo - 1);
+        if (q >= 0)
+            load_cell(w_prv, src, F, static_cast<const S *>(nullptr), plane * q, th.own);
+        load_cell(w_cur, src, F, static_cast<const S *>(nullptr), plane * pz_of(za_lo), th.own);
+        q = pz_of(za_lo + 1);
+        if (q >= 0)
+            load_cell(w_nxt, src, F, static_cast<const S *>(nullptr), plane * q, th.own);
+        weigh(w_prv, a.fc);
+        weigh(w_cur, a.fc);
+    }
+    if (th.hslot >= 0)
+        load_cell(halo, src, F, static_cast<const S *>(nullptr), plane * pz_of(za_lo), th.halo);
+    int i = 0;
+    for (int za = za_lo; za <= za_hi; ++za, ++i) {
+        auto &A = LA[i & 1];
+        auto &B = LB[i & 1];
+        const auto &Bp = LB[(i & 1) ^ 1];
+        if (th.act)
+            A.put(th.l0, w_cur);
+        if (th.hslot >= 0) {
+            weigh(halo, a.fc);
+            A.put(th.hslot, halo);
+        }
+        Off own = th.own, hal = th.halo;
+        asm volatile("" : "+v"(own.b8), "+v"(own.bs), "+v"(own.b1), "+v"(hal.b8), "+v"(hal.bs));
+        if (za < za_hi) {
+            const int q = pz_of(za + 2);
+            if (th.act && q >= 0)
+                load_cell(w_fly, src, F, static_cast<const S *>(nullptr), plane * q, own);
+            if (th.hslot >= 0)
+                load_cell(halo, src, F, static_cast<const S *>(nullptr), plane * pz_of(za + 1),
+                          hal);
+        }
+        __syncthreads();
+        const bool zm = pz_of(za - 1) >= 0, zp = pz_of(za + 1) >= 0;
+        if (th.act) {
+            // first step at plane za, on every A column
+            if (zp)
+                weigh(w_nxt, a.fc);
+            Acc<S> f{};
+            gather_site(A, th.l0, kTwoL0X, th, w_cur, w_prv, zm, w_nxt, zp, p0, f);
+            const int64_t pz = plane * pz_of(za);
+            th_nxt = FID ? ld(TH + pz, own.bs) : S(0);
+            advance_site(w_cur, f, th_nxt, c1);
+            B.put(th.l1, c1);
+            if (th.owned && za >= z0 && za < z1) {
+                r_nxt = MAXR == 1 ? 0 : ld(a.region + pz, own.b1);
+                record_cell<S, FID, MSD, false, MAXR>(c1, r_nxt, acc1);
+            }
+        }
+        const int zb = za - 1;
+        if (th.owned && zb >= z0 && zb < z1) {
+            // second step at plane zb, on the owned columns, from level 1
+            Acc<S> f{};
+            gather_site(Bp, th.l1, kTwoAX, th, v_cur, v_prv, pz_of(zb - 1) >= 0, c1, true, p0,
+                        f);
+            finish_site<S, FID, MSD, false, MAXR>(v_cur, f, th_cur, r_cur, dst,
+                                                  plane * pz_of(zb), own, acc2);
+        }
+        v_prv = v_cur;
+        v_cur = c1;
+        th_cur = th_nxt;
+        r_cur = r_nxt;
+        w_prv = w_cur;
+        w_cur = w_nxt;
+        w_nxt = w_fly;
+    }
+    if (za_hi >= z0 && za_hi < z1) {
+        // the top owned plane below a closed face: its second step has no plane above
+        __syncthreads();
+        if (th.owned) {
+            Acc<S> f{};
+            Off own = th.own;
+            gather_site(LB[(i - 1) & 1], th.l1, kTwoAX, th, v_cur, v_prv, pz_of(za_hi - 1) >= 0,
+                        v_cur, false, p0, f);
+            finish_site<S, FID, MSD, false, MAXR>(v_cur, f, th_cur, r_cur, dst,
+                                                  plane * pz_of(za_hi), own, acc2);
+        }
+    }
+    __syncthreads();
+    block_reduce<MAXR, kThreads / kWave>(acc1, a.R, a.K, part1, p.nblocks, blk, red);
+    __syncthreads();
+    block_reduce<MAXR, kThreads / kWave>(acc2, a.R, a.K, part2, p.nblocks, blk, red);
+}
+
+// Two steps of every lattice in a work list (two-step plans), as k_sweep_tile does one: the
+// first step's sums go to step slot `slot`, the second's to slot + 1.
+template <typename S, bool FID, int MSD, int MAXR>
+__global__ __launch_bounds__(kThreads, LPC_MIN_WAVES) void k_sweep2_tile(
+    const SweepItem *__restrict__ items, const int64_t *__restrict__ prefix, int32_t n_items,
+    int64_t total, int64_t padded, int32_t parity, int64_t slot)
+{
+    const int64_t w = logical_block(blockIdx.x, padded);
+    if (w >= total)
+        return;
+    int lo = 0, hi = n_items - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (prefix[mid] <= w)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    StepArgs a = items[lo].a;
+    const SweepPlan p = items[lo].plan;
+    if (parity) {
+        const StateView t = a.src;
+        a.src = a.dst;
+        a.dst = t;
+    }
+    double *part1 = a.partials + slot * a.K * p.nblocks;
+    sweep2_tile<S, FID, MSD, MAXR>(a, p, w - prefix[lo], part1, part1 + a.K * p.nblocks);
+}
+
+template <typename S, bool FID, int MSD, int MAXR>
 __device__ inline void record_site(const StepArgs &a, const View<S> &v, int64_t i,
                                    RecAcc<MAXR> &acc)
 {
@@ -944,10 +1327,10 @@ __device__ inline void record_site(const StepArgs &a, const View<S> &v, int64_t 
 }
 
 // Record contributions of the current state (no step), on the same tiles as the sweep.
-template <typename S, bool FID, bool MSD, int MAXR>
+template <typename S, bool FID, int MSD, int MAXR>
 __global__ __launch_bounds__(kThreads) void k_record_tile(StepArgs a, SweepPlan p, int64_t padded)
 {
-    __shared__ double red[(kThreads / kWave) * (3 * MAXR + 6)];
+    __shared__ double red[(kThreads / kWave) * record_slots(MAXR, MSD)];
     const int64_t blk = logical_block(blockIdx.x, padded);
     if (blk >= p.nblocks)
         return;
@@ -971,7 +1354,8 @@ __global__ __launch_bounds__(kThreads) void k_record_tile(StepArgs a, SweepPlan 
         for (int z = bz * p.zc; z < z1; ++z)
             record_site<S, FID, MSD, MAXR>(a, src, col + plane * z, acc);
     }
-    block_reduce<MAXR, kThreads / kWave>(acc, a.R, a.K, a.partials, p.nblocks, blk, red);
+    // the autocorrelation entries of a state with no step are zero
+    block_reduce<MAXR, kThreads / kWave, MSD == 2>(acc, a.R, a.K, a.partials, p.nblocks, blk, red);
 }
 
 #if LPC_HOST_PART
@@ -1004,8 +1388,11 @@ __global__ __launch_bounds__(256) void k_finalize(const double *partials, int64_
 __global__ __launch_bounds__(256) void k_finalize_list(const FinalizeItem *__restrict__ items,
                                                        const int64_t *__restrict__ kprefix,
                                                        int32_t n_items, int64_t total_k,
-                                                       int64_t first_row)
+                                                       int64_t first_row,
+                                                       const int64_t *__restrict__ row_offset)
 {
+    if (row_offset)          // a graph replayed per chunk reads its chunk's rows from memory
+        first_row += *row_offset;
     __shared__ double w[4];
     const int64_t s = blockIdx.x / total_k, e = blockIdx.x % total_k;
     int lo = 0, hi = n_items - 1;
@@ -1021,6 +1408,21 @@ __global__ __launch_bounds__(256) void k_finalize_list(const FinalizeItem *__res
     const double t = partial_sum(it.partials + (s * it.K + k) * it.nblocks, it.nblocks, w);
     if (threadIdx.x == 0)
         it.records[(it.row_base + first_row + s) * it.K + k] = t;
+}
+
+// *counter = value, or += add when add is non-zero (one thread): the row counter that the
+// finalisation of a replayed graph reads.
+__global__ void k_set_counter(int64_t *counter, int64_t value, int64_t add)
+{
+    *counter = add != 0 ? *counter + add : value;
+}
+
+// E_i = e^{F_i - c} of the FP64 free energies F (the field the FP64 sweep reads).
+__global__ void k_boltzmann_factors(const double *F, double *E, int64_t n, double fc)
+{
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        E[i] = boltzmann_factor(F[i], fc);
 }
 
 template <typename S>
@@ -1049,6 +1451,10 @@ __global__ void k_init_state(View<S> st, bool fid, bool msd, const double *rho_s
                 st.m1[b][i] = static_cast<S>(0);
                 st.m2[b][i] = static_cast<S>(0);
             }
+        }
+        if (st.v[0]) {
+            for (int b = 0; b < 3; ++b)
+                st.v[b][i] = static_cast<S>(0);
         }
     }
 }
@@ -1163,7 +1569,7 @@ int grid_for(int64_t n, int threads)
 // ---------------------------------------------------------------------------- dispatch
 
 struct RecordLauncher {
-    template <typename S, bool FID, bool MSD, bool, int MAXR>
+    template <typename S, bool FID, int MSD, bool, int MAXR>
     static hipError_t go(const SweepPlan &p, const StepArgs &a, hipStream_t s)
     {
         const int64_t padded = (p.nblocks + 7) / 8 * 8;
@@ -1174,12 +1580,18 @@ struct RecordLauncher {
 };
 
 struct ListLauncher {
-    template <typename S, bool FID, bool MSD, bool EXT, int MAXR>
+    template <typename S, bool FID, int MSD, bool EXT, int MAXR>
     static hipError_t go(const SweepPlan &, const StepArgs &, hipStream_t s, const StepList *L)
     {
         const int64_t padded = (L->total + 7) / 8 * 8;
         const dim3 grid(static_cast<unsigned>(padded)), block(kThreads);
-        if (L->tile_x == kTileLinear) {
+        if (L->tile_x == kTileTwoStep) {
+            if constexpr (EXT || MSD == 2)
+                return hipErrorInvalidValue;        // two-step plans: plain variant, no tags
+            else
+                hipLaunchKernelGGL((k_sweep2_tile<S, FID, MSD, MAXR>), grid, block, 0, s, L->items,
+                                   L->prefix, L->n_items, L->total, padded, L->parity, L->slot);
+        } else if (L->tile_x == kTileLinear) {
             if constexpr (EXT)
                 return hipErrorInvalidValue;        // plans never give the extended variant these
             else
@@ -1199,7 +1611,7 @@ struct ListLauncher {
     }
 };
 
-template <typename L, typename S, bool FID, bool MSD, bool EXT, typename... X>
+template <typename L, typename S, bool FID, int MSD, bool EXT, typename... X>
 hipError_t by_regions(const SweepPlan &p, const StepArgs &a, hipStream_t s, X... x)
 {
     if (a.R == 1)
@@ -1214,7 +1626,10 @@ hipError_t by_regions(const SweepPlan &p, const StepArgs &a, hipStream_t s, X...
 template <typename L, typename S, bool EXT, typename... X>
 hipError_t by_fields(const SweepPlan &p, const StepArgs &a, hipStream_t s, X... x)
 {
-    const bool fid = a.track & 1u, msd = a.track & 2u;
+    const bool fid = a.track & 1u, msd = a.track & 2u, vacf = a.track & kTrackVacf;
+    if (vacf)      // the tags come with the moments
+        return fid ? by_regions<L, S, true, 2, EXT>(p, a, s, x...)
+                   : by_regions<L, S, false, 2, EXT>(p, a, s, x...);
     if (fid && msd)
         return by_regions<L, S, true, true, EXT>(p, a, s, x...);
     if (fid)
@@ -1225,12 +1640,25 @@ hipError_t by_fields(const SweepPlan &p, const StepArgs &a, hipStream_t s, X... 
 }
 
 struct OccupancyQuery {
-    template <typename S, bool FID, bool MSD, bool EXT, int MAXR>
+    template <typename S, bool FID, int MSD, bool EXT, int MAXR>
     static hipError_t go(const SweepPlan &, const StepArgs &, hipStream_t, int *out)
     {
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(
             out, reinterpret_cast<const void *>(&k_sweep_tile<S, FID, MSD, EXT, MAXR, 64>),
             kThreads, 0);
+    }
+};
+
+struct OccupancyQuery2 {
+    template <typename S, bool FID, int MSD, bool EXT, int MAXR>
+    static hipError_t go(const SweepPlan &, const StepArgs &, hipStream_t, int *out)
+    {
+        if constexpr (EXT || MSD == 2)
+            return hipErrorInvalidValue;
+        else
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                out, reinterpret_cast<const void *>(&k_sweep2_tile<S, FID, MSD, MAXR>), kThreads,
+                0);
     }
 };
 
@@ -1241,7 +1669,7 @@ struct OccupancyQuery {
 template <typename S, bool EXT>
 hipError_t step_list_part(const StepList &L, uint32_t track, int32_t maxr, hipStream_t s);
 template <typename S, bool EXT>
-int occupancy_part(uint32_t track, int32_t R);
+int occupancy_part(uint32_t track, int32_t R, int32_t steps_per_pass);
 template <typename S>
 hipError_t record_part(const SweepPlan &plan, const StepArgs &a, hipStream_t s);
 
@@ -1256,13 +1684,16 @@ hipError_t step_list_part(const StepList &L, uint32_t track, int32_t maxr, hipSt
 }
 
 template <typename S, bool EXT>
-int occupancy_part(uint32_t track, int32_t R)
+int occupancy_part(uint32_t track, int32_t R, int32_t steps_per_pass)
 {
     StepArgs a{};
     a.track = track;
     a.R = R;
     int n = 0;
-    if (by_fields<OccupancyQuery, S, EXT>(SweepPlan{}, a, nullptr, &n) != hipSuccess || n < 1)
+    const hipError_t e = steps_per_pass == 2
+                             ? by_fields<OccupancyQuery2, S, EXT>(SweepPlan{}, a, nullptr, &n)
+                             : by_fields<OccupancyQuery, S, EXT>(SweepPlan{}, a, nullptr, &n);
+    if (e != hipSuccess || n < 1)
         return 1;
     return n;
 }
@@ -1276,21 +1707,21 @@ hipError_t record_part(const SweepPlan &plan, const StepArgs &a, hipStream_t s)
 
 #if LPC_PART_IS(0)
 template hipError_t step_list_part<double, false>(const StepList &, uint32_t, int32_t, hipStream_t);
-template int occupancy_part<double, false>(uint32_t, int32_t);
+template int occupancy_part<double, false>(uint32_t, int32_t, int32_t);
 template hipError_t record_part<double>(const SweepPlan &, const StepArgs &, hipStream_t);
 #endif
 #if LPC_PART_IS(1)
 template hipError_t step_list_part<double, true>(const StepList &, uint32_t, int32_t, hipStream_t);
-template int occupancy_part<double, true>(uint32_t, int32_t);
+template int occupancy_part<double, true>(uint32_t, int32_t, int32_t);
 #endif
 #if LPC_PART_IS(2)
 template hipError_t step_list_part<float, false>(const StepList &, uint32_t, int32_t, hipStream_t);
-template int occupancy_part<float, false>(uint32_t, int32_t);
+template int occupancy_part<float, false>(uint32_t, int32_t, int32_t);
 template hipError_t record_part<float>(const SweepPlan &, const StepArgs &, hipStream_t);
 #endif
 #if LPC_PART_IS(3)
 template hipError_t step_list_part<float, true>(const StepList &, uint32_t, int32_t, hipStream_t);
-template int occupancy_part<float, true>(uint32_t, int32_t);
+template int occupancy_part<float, true>(uint32_t, int32_t, int32_t);
 #endif
 
 #if LPC_HOST_PART
@@ -1319,6 +1750,9 @@ int64_t plane_tiles(const Geometry &g, int32_t tx)
 {
     if (tx == kTileLinear)
         return (int64_t(g.nx) * g.ny + kThreads - 1) / kThreads;
+    if (tx == kTileTwoStep)
+        return int64_t((g.nx + kTwoStepTileX - 1) / kTwoStepTileX) *
+               ((g.ny + kTwoStepTileY - 1) / kTwoStepTileY);
     const int32_t ty = kThreads / tx;
     return int64_t((g.nx + tx - 1) / tx) * ((g.ny + ty - 1) / ty);
 }
@@ -1326,12 +1760,47 @@ int64_t plane_tiles(const Geometry &g, int32_t tx)
 int64_t max_sweep_blocks(const Geometry &g)
 {
     int64_t most = 0;
-    for (int32_t tx : {64, 32, 16, kTileLinear}) {
+    for (int32_t tx : {64, 32, 16, kTileLinear, kTileTwoStep}) {
         const int64_t tiles = plane_tiles(g, tx);
         const int64_t gz = std::max<int64_t>((g.nz + 7) / 8, (8192 + tiles - 1) / tiles);
         most = std::max(most, tiles * std::min<int64_t>(g.nz, gz));
     }
     return most;
+}
+
+// Pick the z-chunk of a plan with `tiles` tiles per plane: every resident slot busy until
+// the end (greedy makespan of the chunks against the ideal), few extra planes per chunk
+// (each chunk re-reads the planes around it, mostly from cache; `extra` planes' worth of work
+// per chunk), and a few rounds to absorb uneven progress. A chunk of at least zc_floor planes
+// (or the whole axis): shorter chunks re-read too large a share of planes around them. 4 for
+// a lattice stepped alone; a lattice stepped in a batch takes 16 (the 512-particle batch:
+// 46.0 GSU/s at 16 against 41.3 at 4), since the other lattices fill the device.
+int32_t choose_z_chunk(const Geometry &g, int64_t tiles, int32_t blocks_per_cu, int32_t cus,
+                       int32_t zc_floor, double extra)
+{
+    const int64_t conc = std::max(1, blocks_per_cu) * static_cast<int64_t>(std::max(1, cus));
+    const int64_t gz_cap = std::max<int64_t>((g.nz + 7) / 8, (8192 + tiles - 1) / tiles);
+    const int64_t gz_max = std::min<int64_t>(g.nz, gz_cap);
+    const int32_t zc_min = std::min(g.nz, std::max(1, zc_floor));
+    double best = -1.0;
+    int32_t best_zc = g.nz;
+    for (int64_t gz = 1; gz <= gz_max; ++gz) {
+        const int32_t zc = static_cast<int32_t>((g.nz + gz - 1) / gz);
+        const int64_t gze = (g.nz + zc - 1) / zc;
+        if (gze != gz || zc < zc_min)
+            continue;
+        const int64_t T = tiles * gze;
+        const int64_t rounds = (T + conc - 1) / conc;
+        const double ideal = static_cast<double>(tiles) * g.nz / static_cast<double>(conc);
+        const double fill = ideal / static_cast<double>(rounds * zc);
+        const double pro = zc / (zc + extra);
+        const double eff = fill * pro * (1.0 - 0.05 / static_cast<double>(rounds));
+        if (eff > best + 1e-12) {
+            best = eff;
+            best_zc = zc;
+        }
+    }
+    return best_zc;
 }
 
 SweepPlan make_plan(const Geometry &g, int32_t blocks_per_cu, int32_t cus, int32_t tile_x,
@@ -1357,36 +1826,23 @@ SweepPlan make_plan(const Geometry &g, int32_t blocks_per_cu, int32_t cus, int32
         p.gy = (g.ny + p.ty - 1) / p.ty;
     }
     const int64_t tiles = static_cast<int64_t>(p.gx) * p.gy;
-    const int64_t conc = std::max(1, blocks_per_cu) * static_cast<int64_t>(std::max(1, cus));
-    const int64_t gz_cap = std::max<int64_t>((g.nz + 7) / 8, (8192 + tiles - 1) / tiles);
-    const int64_t gz_max = std::min<int64_t>(g.nz, gz_cap);
-    // Pick the z-chunk: every resident slot busy until the end (greedy makespan of the
-    // chunks against the ideal), few extra planes per chunk (each chunk re-reads the two
-    // planes around it, mostly from cache), and a few rounds to absorb uneven progress.
-    // A chunk of at least zc_floor planes (or the whole axis): shorter chunks re-read too
-    // large a share of planes around them. 4 for a lattice stepped alone; a lattice stepped
-    // in a batch takes 16 (the 512-particle batch: 46.0 GSU/s at 16 against 41.3 at 4),
-    // since the other lattices fill the device.
-    const int32_t zc_min = std::min(g.nz, std::max(1, zc_floor));
-    double best = -1.0;
-    int32_t best_zc = g.nz;
-    for (int64_t gz = 1; gz <= gz_max; ++gz) {
-        const int32_t zc = static_cast<int32_t>((g.nz + gz - 1) / gz);
-        const int64_t gze = (g.nz + zc - 1) / zc;
-        if (gze != gz || zc < zc_min)
-            continue;
-        const int64_t T = tiles * gze;
-        const int64_t rounds = (T + conc - 1) / conc;
-        const double ideal = static_cast<double>(tiles) * g.nz / static_cast<double>(conc);
-        const double fill = ideal / static_cast<double>(rounds * zc);
-        const double pro = zc / (zc + 0.5);
-        const double eff = fill * pro * (1.0 - 0.05 / static_cast<double>(rounds));
-        if (eff > best + 1e-12) {
-            best = eff;
-            best_zc = zc;
-        }
-    }
-    p.zc = best_zc;
+    p.zc = choose_z_chunk(g, tiles, blocks_per_cu, cus, zc_floor, 0.5);
+    p.gz = (g.nz + p.zc - 1) / p.zc;
+    p.nblocks = tiles * p.gz;
+    return p;
+}
+
+SweepPlan make_plan2(const Geometry &g, int32_t blocks_per_cu, int32_t cus, int32_t zc_floor)
+{
+    SweepPlan p{};
+    p.tx = kTileTwoStep;
+    p.ty = kTwoStepTileY;
+    p.gx = (g.nx + kTwoStepTileX - 1) / kTwoStepTileX;
+    p.gy = (g.ny + kTwoStepTileY - 1) / kTwoStepTileY;
+    const int64_t tiles = static_cast<int64_t>(p.gx) * p.gy;
+    // a chunk's first step also runs on the plane on either side of it, and its level-0
+    // window reads two planes on either side
+    p.zc = choose_z_chunk(g, tiles, blocks_per_cu, cus, zc_floor, 2.0);
     p.gz = (g.nz + p.zc - 1) / p.zc;
     p.nblocks = tiles * p.gz;
     return p;
@@ -1404,20 +1860,28 @@ int32_t linear_tile_max_nx(int32_t precision, uint32_t track)
 {
     if (track & kVariantExtended)
         return 0;
-    const bool fid = track & 1u, msd = track & 2u;
-    if (precision == 0)
-        return fid ? (msd ? linear_nx_max<double, true, true>() : linear_nx_max<double, true, false>())
-                   : (msd ? linear_nx_max<double, false, true>() : linear_nx_max<double, false, false>());
-    return fid ? (msd ? linear_nx_max<float, true, true>() : linear_nx_max<float, true, false>())
-               : (msd ? linear_nx_max<float, false, true>() : linear_nx_max<float, false, false>());
+    const bool fid = track & 1u;
+    const int mom = (track & kTrackVacf) ? 2 : ((track & 2u) ? 1 : 0);
+    if (precision == 0) {
+        if (mom == 2)
+            return fid ? linear_nx_max<double, true, 2>() : linear_nx_max<double, false, 2>();
+        return fid ? (mom ? linear_nx_max<double, true, 1>() : linear_nx_max<double, true, 0>())
+                   : (mom ? linear_nx_max<double, false, 1>() : linear_nx_max<double, false, 0>());
+    }
+    if (mom == 2)
+        return fid ? linear_nx_max<float, true, 2>() : linear_nx_max<float, false, 2>();
+    return fid ? (mom ? linear_nx_max<float, true, 1>() : linear_nx_max<float, true, 0>())
+               : (mom ? linear_nx_max<float, false, 1>() : linear_nx_max<float, false, 0>());
 }
 
-int sweep_blocks_per_cu(int32_t precision, uint32_t track, int32_t R)
+int sweep_blocks_per_cu(int32_t precision, uint32_t track, int32_t R, int32_t steps_per_pass)
 {
     const bool ext = track & kVariantExtended;
+    const int k = steps_per_pass;
     if (precision == 0)
-        return ext ? occupancy_part<double, true>(track, R) : occupancy_part<double, false>(track, R);
-    return ext ? occupancy_part<float, true>(track, R) : occupancy_part<float, false>(track, R);
+        return ext ? occupancy_part<double, true>(track, R, k)
+                   : occupancy_part<double, false>(track, R, k);
+    return ext ? occupancy_part<float, true>(track, R, k) : occupancy_part<float, false>(track, R, k);
 }
 
 hipError_t launch_step_list(const StepList &L, int32_t precision, uint32_t track, int32_t maxr,
@@ -1439,12 +1903,19 @@ hipError_t launch_record(const SweepPlan &plan, const StepArgs &a, hipStream_t s
 }
 
 hipError_t launch_finalize_list(const FinalizeItem *items, const int64_t *kprefix, int32_t n_items,
-                                int64_t total_k, int64_t steps, int64_t first_row, hipStream_t s)
+                                int64_t total_k, int64_t steps, int64_t first_row, hipStream_t s,
+                                const int64_t *row_offset)
 {
     if (steps <= 0 || total_k <= 0)
         return hipSuccess;
     hipLaunchKernelGGL(k_finalize_list, dim3(static_cast<unsigned>(steps * total_k)), dim3(256), 0,
-                       s, items, kprefix, n_items, total_k, first_row);
+                       s, items, kprefix, n_items, total_k, first_row, row_offset);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_counter(int64_t *counter, int64_t value, int64_t add, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(1), 0, s, counter, value, add);
     return hipGetLastError();
 }
 
@@ -1527,6 +1998,13 @@ hipError_t launch_stream_columns(const ColumnArrays &c, int32_t nx, int32_t ny, 
     const int64_t blocks = int64_t(tiles_x) * tiles_y * ((nz + zc - 1) / zc);
     hipLaunchKernelGGL(k_stream_columns, dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0, s,
                        c, nx, ny, nz, zc, tiles_x, tiles_y);
+    return hipGetLastError();
+}
+
+hipError_t launch_boltzmann_factors(const double *F, double *E, int64_t n, double fc,
+                                    hipStream_t s)
+{
+    hipLaunchKernelGGL(k_boltzmann_factors, dim3(grid_for(n, 256)), dim3(256), 0, s, F, E, n, fc);
     return hipGetLastError();
 }
 

@@ -65,7 +65,7 @@ def make_config(shape_xyz, bc=("periodic",) * 3, precision="fp64", track=("fid",
     cfg.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
     t = 0
     for name in track:
-        t |= {"fid": N.TRACK_FID, "msd": N.TRACK_MSD}[name]
+        t |= {"fid": N.TRACK_FID, "msd": N.TRACK_MSD, "vacf": N.TRACK_VACF}[name]
     cfg.track = t
     cfg.n_regions = int(n_regions)
     cfg.options = (N.OPT_MOBILITY if mobility else 0) | (N.OPT_BATCHED if batched else 0)
@@ -375,6 +375,15 @@ class Batch:
                    ctypes.c_void_p(self.arena.data_ptr()), nbytes,
                    ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
         self._h = h
+
+    def use_graph(self, enable: bool = True):
+        """Replay captured graphs per chunk of steps (default) or launch every step."""
+        N.call("lpc_batch_use_graph", self._h, 1 if enable else 0)
+
+    def describe(self) -> str:
+        buf = ctypes.create_string_buffer(256)
+        N.call("lpc_batch_describe", self._h, buf, len(buf))
+        return buf.value.decode()
 
     def run(self, n_steps):
         """n_steps: one count per lattice (or a single int for all)."""

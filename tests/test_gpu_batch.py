@@ -140,3 +140,42 @@ def test_batch_errors():
     assert a.steps_done == 10 and c.steps_done == 20
     for lat in (a, b, c):
         lat.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_graph_replays_equal_direct_launches(precision):
+    """Graph replays (one captured chunk of steps replayed per chunk, its record rows from a
+    device counter) against every step launched directly and against solo runs: every
+    replay, with eager work and synchronisations between batch runs, ends on the same bits."""
+    from paper_2603_22553_amd.lattice import Batch
+    items = mixed_set()
+    runs = [[1400, 1200, 1300, 1400, 1040, 600], [600, 0, 888, 1, 0, 600], [2, 2, 2, 2, 2, 2]]
+    total = [sum(r[k] for r in runs) for k in range(len(items))]
+    results = {}
+    for graph in (True, False):
+        lats = [make(f, precision, 3600, bc) for f, bc in items]
+        with Batch(lats) as b:
+            b.use_graph(graph)
+            for r in runs:
+                b.run(r)
+                # eager work on the lattices' own streams between the batch runs
+                for lat in lats:
+                    lat.population()
+            d = b.describe()
+        if graph:
+            assert "graphs on" in d and " 0 chunks replayed" not in d, d
+        else:
+            assert "graphs off" in d and " 0 chunks replayed" in d, d
+        results[graph] = [(lat.records(), lat.population(), lat.magnetization()) for lat in lats]
+        for lat, n in zip(lats, total):
+            assert lat.steps_done == n
+            lat.check()
+            lat.close()
+    for a, b in zip(results[True], results[False]):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+    # and the graph-replayed batch against one lattice alone
+    f, bc = items[0]
+    with make(f, precision, 3600, bc) as lat:
+        lat.run(total[0])
+        assert np.array_equal(lat.records(), results[True][0][0])

@@ -202,8 +202,31 @@ def test_plan_override_and_autotune(tmp_path):
             assert e.value.status == N.LPC_ERR_ARG
     cache = str(tmp_path / "tune.json")
     tx, zc = autotune.tune((70, 20, 33), n_regions=2, steps=5, cache_path=cache)
-    assert (tx, zc) in autotune.candidates((70, 20, 33), zc) or tx in (64, 32, 16)
+    assert tx in (64, 32, 16, autotune.LINEAR, autotune.TWO_STEP)
     assert autotune.tune((70, 20, 33), n_regions=2, steps=5, cache_path=cache) == (tx, zc)
+
+
+def test_autotune_configurations(tmp_path):
+    """The tuner builds its probe lattices from the target's configuration (reservoir axes,
+    mobility field, batched planning), keys its cache on it, and sets plans the lattices
+    take: a reservoir or mobility lattice gets a block-tile, one-step plan; a batched
+    lattice is timed in a batch of copies and gets z-chunks of at least 16 planes."""
+    from paper_2603_22553_amd import autotune
+    from paper_2603_22553_amd.lattice import Lattice
+    cache = str(tmp_path / "tune.json")
+    shape = (40, 24, 36)
+    with Lattice(shape, bc=("reservoir", "periodic", "closed"), n_regions=2, max_records=3) as a, \
+            Lattice(shape, mobility=True, n_regions=2, max_records=3) as b, \
+            Lattice(shape, precision="mixed", n_regions=2, max_records=3, batched=True) as c:
+        plans = autotune.apply_all([a, b, c], steps=3, warmup=1, cache_path=cache)
+        assert len(plans) == 3
+        for lat in (a, b):
+            assert lat.plan["tile_x"] in (64, 32, 16) and "steps per pass 1" in lat.describe()
+        assert c.plan["zc"] >= 16 and "steps per pass 1" in c.describe()
+    import json
+    keys = list(json.load(open(cache)))
+    assert any("reservoir" in k for k in keys) and any("mobility" in k for k in keys)
+    assert any("batched" in k for k in keys)
 
 
 def test_stream_columns_calibration():
