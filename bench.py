@@ -346,7 +346,8 @@ def workload_batch(args):
         "data": "synthetic",
         "config": {"workload": f"{len(fields)} particles, radius 8-48, box 2R+8, one batched "
                                "sweep per step, FID + MSD", "sites": sites},
-        "roofline": roofline(sites, prec, ms / steps),
+        "roofline": roofline(sites, prec, ms / steps, traffic=measured_traffic(
+            "sweep_batch_512particles_hbm_traffic.md", "mixed")),
         "launch": graph_desc,
         "direct_launches": {"value": round(sites * steps / (ms_direct * 1e-3) / 1e9, 4),
                             "unit": "GSU/s", "ms_per_step": round(ms_direct / steps, 6),
@@ -462,7 +463,8 @@ def workload_porous(args):
     for p, r in res.items():
         ms_step = r["ms"] / args.steps
         # the mobility field is one more field read per site-update
-        rl = roofline(f.n_sites, p, ms_step, mobility=True, n_regions=f.n_regions)
+        rl = roofline(f.n_sites, p, ms_step, mobility=True, n_regions=f.n_regions,
+                      traffic=measured_traffic("sweep_porous_256cubed_hbm_traffic.md", p))
         entry = {"value": round(r["gsu_s"], 4), "unit": "GSU/s", "ms_per_step": round(ms_step, 6),
                  "dtype": "f64" if p == "fp64" else "f32-storage/f64-sums", "roofline": rl,
                  "results": {"peak_ppm": round(r["peak"], 4), "D_over_Dbulk": r["ratio"],
@@ -510,7 +512,9 @@ def workload_supercap(args):
                                    "100x100x300, closed in z, tau 1 ms, 282 MHz, FID + MSD, "
                                    "the four systems in one batch",
                        "runs": len(runs), "sites": runs[0]["sites"], "precision": prec},
-            "roofline": roofline(sum(r["sites"] for r in runs), prec, ms_step, n_regions=3),
+            "roofline": roofline(sum(r["sites"] for r in runs), prec, ms_step, n_regions=3,
+                                 traffic=measured_traffic(
+                                     "sweep_supercap_100x100x300_hbm_traffic.md", prec)),
             "results": {"table": table, "wall_s_including_setup": round(wall, 1)}}
 
 
@@ -543,8 +547,8 @@ def workload_equilibrate(args):
     out = None
     for p, r in res.items():
         ms_step = r["ms"] / args.steps
-        rl = roofline(f.n_sites, p, ms_step, track=(), n_regions=f.n_regions)
-        rl["traffic"] = None
+        rl = roofline(f.n_sites, p, ms_step, track=(), n_regions=f.n_regions,
+                      traffic=measured_traffic("sweep_equilibrate_256cubed_hbm_traffic.md", p))
         rl["check_bytes_per_site_update"] = round(16.0 / args.check_every, 3)
         entry = {"value": round(r["gsu_s"], 4), "unit": "GSU/s", "ms_per_step": round(ms_step, 6),
                  "dtype": "f64" if p == "fp64" else "f32-probabilities/f64-populations",
@@ -567,20 +571,65 @@ def workload_equilibrate(args):
 
 # ------------------------------------------------------------------- serving
 
+def _request_fields(req):
+    from paper_2603_22553_amd import synth
+    return synth.request_fields(req)
+
+
+def generate_trace(rate, n):
+    """Jobs of one trace with their inputs, generated on the host cores (worker processes
+    forked before this process touches the GPU)."""
+    import multiprocessing as mp
+    from paper_2603_22553_amd import serve, synth
+    trace = synth.serving_trace(n, rate_hz=rate)
+    t = time.perf_counter()
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+        fields = pool.map(_request_fields, trace, chunksize=8)
+    jobs = [serve.Job(r.job_id, r.arrival_s, f, r.n_steps) for r, f in zip(trace, fields)]
+    print(f"# generated {len(jobs)} requests at {rate}/s in {time.perf_counter() - t:.1f} s",
+          file=sys.stderr, flush=True)
+    return jobs
+
+
+def serve_trace(args, rate, jobs):
+    """Serves one trace of jobs: (stats, jobs)."""
+    from paper_2603_22553_amd import serve
+    n = len(jobs)
+    ex = serve.GpuExecutor(keep_fid=True, tune=bool(args.tune_serve))
+    if args.tune_serve:
+        # plans of every distinct box, tuned (or read from the tuning cache) before the clock
+        from paper_2603_22553_amd import autotune
+        t = time.perf_counter()
+        shapes = sorted({j.fields.F.shape for j in jobs})
+        for nz, ny, nx in shapes:
+            autotune.tune((nx, ny, nz), precision="mixed", track=("fid",), n_regions=2,
+                          batched=True)
+        print(f"# tuned {len(shapes)} box shapes in {time.perf_counter() - t:.1f} s",
+              file=sys.stderr, flush=True)
+    srv = serve.Server(ex, hbm_budget_bytes=200e9, tick_steps=args.tick_steps)
+    st = srv.run(jobs, progress=lambda s: print(f"# serving {rate}/s: {s}", file=sys.stderr,
+                                                 flush=True))
+    su = sum(j.n_sites * j.n_steps for j in jobs)
+    st["offered_gsu_s"] = su / max(max(j.arrival_s for j in jobs), 1e-9) / 1e9
+    st["served_gsu_s"] = su / st["makespan_s"] / 1e9
+    st["arrival_span_s"] = max(j.arrival_s for j in jobs)
+    print(f"# served {n} requests at {rate}/s: {st['spectra_per_s']:.3f} spectra/s, p50 "
+          f"{st['latency_p50_s']:.1f} s, p99 {st['latency_p99_s']:.1f} s", file=sys.stderr,
+          flush=True)
+    return st, jobs
+
+
 def workload_serve(args):
     import numpy as np
-    from paper_2603_22553_amd import serve, synth
-    trace = synth.serving_trace(args.serve_requests, rate_hz=args.serve_rate)
-    t = time.perf_counter()
-    jobs = [serve.Job(r.job_id, r.arrival_s, synth.request_fields(r), r.n_steps) for r in trace]
-    print(f"# generated {len(jobs)} requests in {time.perf_counter() - t:.1f} s",
-          file=sys.stderr, flush=True)
-    srv = serve.Server(serve.GpuExecutor(keep_fid=True), hbm_budget_bytes=200e9,
-                       tick_steps=args.tick_steps)
-    st = srv.run(jobs)
-    su = sum(j.n_sites * j.n_steps for j in jobs)
-    # the same first requests one at a time through the single-lattice path
     from paper_2603_22553_amd.lattice import Lattice
+    rates = [float(r) for r in args.serve_rates.split(",")]
+    main_rate = rates[0]
+    traces = [generate_trace(main_rate, args.serve_requests)]
+    traces += [generate_trace(r, args.serve_sweep_requests) for r in rates[1:]]
+    import torch
+    assert torch.cuda.is_available(), "no GPU"
+    st, jobs = serve_trace(args, main_rate, traces[0])
+    # the same first requests one at a time through the single-lattice path
     n_alone = min(len(jobs), args.serve_alone)
     t = time.perf_counter()
     su_alone = 0
@@ -594,22 +643,42 @@ def workload_serve(args):
             assert np.array_equal(lat.fid(), j.result["fid"]), "served result differs from alone"
             su_alone += j.n_sites * j.n_steps
     alone_s = time.perf_counter() - t
+    r3 = lambda v: round(float(v), 3)
     out = {
-        "metric": "served spectra/s with p50/p99 latency", "value": round(st["spectra_per_s"], 4),
+        "metric": "served spectra/s with p50/p99 latency", "value": r3(st["spectra_per_s"]),
         "unit": "spectra/s", "n_gpus": 1, "steps": None, "warmup": 0,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32-storage/f64-sums", "data": "synthetic",
-        "config": {"workload": f"{len(jobs)} Poisson arrivals at {args.serve_rate}/s, box sides "
+        "config": {"workload": f"{len(jobs)} Poisson arrivals at {main_rate}/s, box sides "
                                "16-192 log-uniform, 5000-40000 steps, FID only, 200 GB budget, "
-                               f"tick {args.tick_steps} steps"},
-        "latency_p50_s": round(st["latency_p50_s"], 3), "latency_p99_s": round(st["latency_p99_s"], 3),
-        "queue_p50_s": round(st["queue_p50_s"], 3), "queue_p99_s": round(st["queue_p99_s"], 3),
-        "service_p50_s": round(st["service_p50_s"], 3), "service_p99_s": round(st["service_p99_s"], 3),
-        "gsu_s": round(su / st["makespan_s"] / 1e9, 3),
-        "offered_gsu_s": round(su / max(j.arrival_s for j in jobs) / 1e9, 3),
+                               f"ticks of at most {args.tick_steps} steps"},
+        "latency_p50_s": r3(st["latency_p50_s"]), "latency_p99_s": r3(st["latency_p99_s"]),
+        "queue_p50_s": r3(st["queue_p50_s"]), "queue_p99_s": r3(st["queue_p99_s"]),
+        "service_p50_s": r3(st["service_p50_s"]), "service_p99_s": r3(st["service_p99_s"]),
+        "gsu_s": r3(st["served_gsu_s"]), "offered_gsu_s": r3(st["offered_gsu_s"]),
+        "ticks": st["ticks"], "makespan_s": r3(st["makespan_s"]),
         "alone": {"requests": n_alone, "spectra_per_s": round(n_alone / alone_s, 4),
-                  "gsu_s": round(su_alone / alone_s / 1e9, 3), "bitwise_equal_to_served": True},
+                  "gsu_s": r3(su_alone / alone_s / 1e9), "bitwise_equal_to_served": True},
     }
+    if len(rates) > 1:
+        # lower arrival rates with shorter traces: where the server keeps up, the queueing
+        # delay stays bounded; the saturation throughput is the rate served at the highest load
+        sweep = []
+        for rate, tr in zip(rates[1:], traces[1:]):
+            s, _ = serve_trace(args, rate, tr)
+            keeps_up = s["spectra_per_s"] >= 0.9 * rate and s["queue_p99_s"] <= s["service_p99_s"]
+            sweep.append({"rate_hz": rate, "requests": args.serve_sweep_requests,
+                          "spectra_per_s": r3(s["spectra_per_s"]),
+                          "latency_p50_s": r3(s["latency_p50_s"]),
+                          "latency_p99_s": r3(s["latency_p99_s"]),
+                          "queue_p99_s": r3(s["queue_p99_s"]),
+                          "service_p99_s": r3(s["service_p99_s"]),
+                          "gsu_s": r3(s["served_gsu_s"]), "offered_gsu_s": r3(s["offered_gsu_s"]),
+                          "p99_bounded": bool(keeps_up)})
+        out["rate_sweep"] = sweep
+        bounded = [s["rate_hz"] for s in sweep if s["p99_bounded"]]
+        out["highest_rate_with_bounded_p99_hz"] = max(bounded) if bounded else None
+    out["saturation_spectra_per_s"] = out["value"]
     if args.serve_oracle > 0:
         # a 1 % sample of the served jobs against the oracle, over a prefix of each job's
         # steps that the oracle finishes in seconds (the served FID rows of that prefix are the
@@ -760,8 +829,14 @@ def main():
     ap.add_argument("--tune", type=int, default=1,
                     help="batch workload: plans from the autotuner (each distinct box timed in a "
                          "batch of copies); 0: the automatic batch plans")
-    ap.add_argument("--serve-requests", type=int, default=200)
-    ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-rates", default="20",
+                    help="comma-separated arrival rates (1/s): the first serves --serve-requests "
+                         "(the headline), the others --serve-sweep-requests each")
+    ap.add_argument("--serve-sweep-requests", type=int, default=300)
+    ap.add_argument("--tune-serve", type=int, default=0,
+                    help="serving: plans from the autotuner for every distinct box (tuned before "
+                         "the clock starts)")
     ap.add_argument("--serve-alone", type=int, default=20)
     ap.add_argument("--serve-oracle", type=int, default=1,
                     help="served jobs compared with the oracle (every 100th job, cheapest first)")
@@ -784,8 +859,9 @@ def main():
     if args.cpu_steps is None:
         args.cpu_steps = {"film": 12, "particle": 20}.get(args.workload, 0)
 
-    import torch
-    assert torch.cuda.is_available(), "no GPU"
+    if args.workload != "serve":          # serving generates its inputs before the GPU starts
+        import torch
+        assert torch.cuda.is_available(), "no GPU"
     fn = {"particle": workload_particle, "batch": workload_batch, "film": workload_film,
           "serve": workload_serve, "copy": workload_copy,
           "equilibrate": workload_equilibrate, "porous": workload_porous,

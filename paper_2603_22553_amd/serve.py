@@ -2,11 +2,19 @@
 
 Spectrum / adsorption jobs (one carbon particle each) arrive over time. The server keeps
 the lattices of admitted jobs resident on the GPU, admits new jobs whenever the device
-memory budget allows, and advances all resident jobs together, `tick_steps` steps at a
-time, with one batched sweep (lpc_batch_run): jobs that arrive while others run join at
-the next tick, and finished jobs leave at the end of the tick in which their last step
-ran. Each job's result is bit for bit the one it gets when run alone, because the batched
+memory budget allows, and advances all resident jobs together with one batched sweep
+(lpc_batch_run) per tick: jobs that arrive while others run join at the next tick, and
+finished jobs leave at the end of the tick in which their last step ran. A tick advances
+every resident job by the same number of steps, at most `tick_steps` and at most what the
+job closest to its end still needs, so that each tick is one phase of the batch (one table
+upload, launches replayed from one captured graph) and a finished job frees its memory at
+once. Each job's result is bit for bit the one it gets when run alone, because the batched
 sweep keeps every lattice's own tiles and reduction order.
+
+With an executor that steps asynchronously (GpuExecutor), admission overlaps the sweep: the
+server queues a tick, then, while the device runs it, starts the jobs that have arrived (field
+uploads and start on a second stream; they join at the next tick), and only then waits for
+the tick and reads the results of the jobs it finished.
 
 The executor is pluggable: GpuExecutor drives liblpc; tests drive the scheduler with a
 CPU stand-in and a virtual clock.
@@ -47,16 +55,27 @@ class Job:
 
 
 class GpuExecutor:
-    """Runs jobs on one GPU through liblpc: float storage with double sums, FID only."""
+    """Runs jobs on one GPU through liblpc: float storage with double sums, FID only.
+
+    The batched sweep runs on the device's current stream; each job's lattice (its field
+    uploads, start and post-processing) lives on a second stream of the same priority, so
+    that those overlap the sweep of the jobs already running. lpc_batch_run waits for the
+    lattices' own streams before it steps them. With `tune`, each box configuration's plan
+    comes from the autotuner (timed once per configuration, in a batch of copies)."""
 
     def __init__(self, precision: str = "mixed", track=("fid",), device: str = "cuda",
-                 keep_fid: bool = True):
+                 keep_fid: bool = True, tune: bool = False):
+        import torch
         from . import lattice as _lat  # loads liblpc; fails loudly if it is not built
         self._lat = _lat
+        self._torch = torch
         self.precision = precision
         self.track = tuple(track)
         self.device = device
         self.keep_fid = keep_fid
+        self.tune = tune
+        self.side = torch.cuda.Stream(device=device)          # default priority
+        self.main = torch.cuda.current_stream(device)
 
     def _cfg(self, job: Job):
         nz, ny, nx = job.fields.F.shape
@@ -71,15 +90,30 @@ class GpuExecutor:
         nz, ny, nx = job.fields.F.shape
         lat = self._lat.Lattice((nx, ny, nz), job.bc, self.precision, self.track,
                                 job.fields.n_regions, max_records=job.n_steps + 1,
-                                device=self.device, batched=True)
+                                device=self.device, batched=True, stream=self.side)
+        if self.tune:
+            from . import autotune
+            autotune.apply(lat)
         lat.set_fields(job.fields)
         lat.init_state("uniform")
         return lat
 
+    def step_async(self, handles: list, steps: List[int]):
+        """Queues one tick on the main stream and returns at once (the batch waits for the
+        lattices' own streams first); wait() blocks until it has run."""
+        b = self._lat.Batch(handles, stream=self.main)
+        b.run(steps)
+        done = self._torch.cuda.Event()
+        done.record(self.main)
+        return b, done
+
+    def wait(self, token) -> None:
+        b, done = token
+        done.synchronize()
+        b.close()
+
     def step(self, handles: list, steps: List[int]) -> None:
-        with self._lat.Batch(handles) as b:
-            b.run(steps)
-        handles[0].synchronize()
+        self.wait(self.step_async(handles, steps))
 
     def finish(self, job: Job, handle) -> dict:
         out = {"peak_ppm": handle.peak_ppm()}
@@ -98,7 +132,7 @@ class Server:
 
     def __init__(self, executor, hbm_budget_bytes: float = 200e9, tick_steps: int = 2000,
                  clock: Callable[[], float] = time.perf_counter,
-                 sleep: Callable[[float], None] = time.sleep):
+                 sleep: Callable[[float], None] = time.sleep, uniform_ticks: bool = True):
         self.ex = executor
         self.budget = float(hbm_budget_bytes)
         self.tick_steps = int(tick_steps)
@@ -115,6 +149,9 @@ class Server:
         self.site_updates = 0
         self._t0 = None
         self._cancel_ids = set()
+        self.uniform_ticks = uniform_ticks
+        self.overlap = hasattr(executor, "step_async")
+        self._to_retire: list = []       # finished in the last tick, results not yet read
 
     # ----------------------------------------------------------------- requests
     def now(self) -> float:
@@ -165,8 +202,33 @@ class Server:
         job.status = "done"
         self.done.append(job)
 
+    def _tick_steps(self) -> List[int]:
+        left = [j.n_steps - j.steps_done for j, _ in self.resident]
+        if self.uniform_ticks:
+            s = min(self.tick_steps, min(left))
+            return [s] * len(left)
+        return [min(self.tick_steps, n) for n in left]
+
+    def _account(self, steps) -> None:
+        keep = []
+        for (job, h), s in zip(self.resident, steps):
+            job.steps_done += s
+            self.site_updates += s * job.n_sites
+            if job.steps_done >= job.n_steps:
+                self._to_retire.append((job, h))
+            else:
+                keep.append((job, h))
+        self.resident = keep
+
+    def _drain_retired(self) -> None:
+        for job, h in self._to_retire:
+            self._retire(job, h)
+        self._to_retire = []
+
     def tick(self) -> bool:
         """Admits what fits, advances every resident job; False when nothing is left."""
+        if self.overlap:
+            return self._tick_overlapped()
         self._admit()
         if self._cancel_ids:
             keep = []
@@ -184,27 +246,66 @@ class Server:
             if wait > 0:
                 self.sleep(wait)
             return True
-        steps = [min(self.tick_steps, j.n_steps - j.steps_done) for j, _ in self.resident]
+        steps = self._tick_steps()
         self.ex.step([h for _, h in self.resident], steps)
         self.ticks += 1
+        self._account(steps)
+        self._drain_retired()
+        return True
+
+    def _tick_overlapped(self) -> bool:
+        """One tick with the admission work beside it: queue the tick, start the jobs that
+        join at the next tick (their uploads run on the second stream while the device sweeps),
+        wait, then read the results of the jobs that finished."""
+        self._apply_cancels()
+        if not self.resident:
+            self._admit()
+            if not self.resident:
+                if not self.pending:
+                    return False
+                wait = self.pending[0].arrival_s - self.now()
+                if wait > 0:
+                    self.sleep(wait)
+                return True
+        steps = self._tick_steps()
+        token = self.ex.step_async([h for _, h in self.resident], steps)
+        self.ticks += 1
+        running = self.resident
+        self.resident = []
+        self._admit()                      # uploads of jobs that join at the next tick
+        admitted = self.resident
+        self.resident = running
+        self.ex.wait(token)
+        self._account(steps)
+        self._drain_retired()
+        self.resident.extend(admitted)
+        return True
+
+    def _apply_cancels(self) -> None:
+        if not self._cancel_ids:
+            return
         keep = []
-        for (job, h), s in zip(self.resident, steps):
-            job.steps_done += s
-            self.site_updates += s * job.n_sites
-            if job.steps_done >= job.n_steps:
-                self._retire(job, h)
+        for job, h in self.resident:
+            if job.job_id in self._cancel_ids:
+                self._retire(job, h, cancelled=True)
             else:
                 keep.append((job, h))
         self.resident = keep
-        return True
+        self._cancel_ids.clear()
 
-    def run(self, jobs: List[Job]) -> dict:
-        """Serves a trace (jobs sorted by arrival) to completion and returns statistics."""
+    def run(self, jobs: List[Job], progress: Optional[Callable[[dict], None]] = None,
+            progress_every_s: float = 30.0) -> dict:
+        """Serves a trace (jobs sorted by arrival) to completion and returns statistics;
+        `progress` (optional) receives a short status dict every progress_every_s seconds."""
         self._t0 = self.clock()
         for j in sorted(jobs, key=lambda j: j.arrival_s):
             self.submit(j)
+        last = self.now()
         while self.tick():
-            pass
+            if progress is not None and self.now() - last >= progress_every_s:
+                last = self.now()
+                progress({"t_s": last, "done": len(self.done), "resident": len(self.resident),
+                          "pending": len(self.pending), "ticks": self.ticks})
         return self.stats()
 
     def stats(self) -> dict:

@@ -148,3 +148,44 @@ def test_rejection_and_cancellation(oracle):
     st = srv.stats()
     assert st["jobs_cancelled"] == 2 and st["jobs_rejected"] == 1 and st["jobs_done"] == 4
     assert srv.used_bytes == 0
+
+
+class AsyncOracleExecutor(OracleExecutor):
+    """The oracle stand-in with the asynchronous interface of the GPU executor: a tick is
+    queued by step_async and completed by wait; starts record whether a tick was in flight."""
+
+    def __init__(self, oracle, clock):
+        super().__init__(oracle, clock)
+        self.inflight = False
+        self.starts_during_tick = 0
+
+    def start(self, job):
+        if self.inflight:
+            self.starts_during_tick += 1
+        return super().start(job)
+
+    def step_async(self, handles, steps):
+        self.inflight = True
+        return handles, steps
+
+    def wait(self, token):
+        self.step(*token)
+        self.inflight = False
+
+
+def test_overlapped_ticks_match_solo_runs(oracle):
+    """With an asynchronous executor the server admits jobs while a tick is queued; every job
+    still ends on its solo run's bits, and every tick advances all resident jobs by the same
+    number of steps (one batch phase), never past the job nearest its end."""
+    clock = Clock()
+    ex = AsyncOracleExecutor(oracle, clock)
+    srv = serve.Server(ex, hbm_budget_bytes=1e12, tick_steps=100, clock=clock, sleep=clock.sleep)
+    assert srv.overlap
+    jobs = trace(12)
+    st = srv.run(jobs)
+    assert st["jobs_done"] == 12
+    for j in jobs:
+        assert np.array_equal(j.result["fid"], solo_fid(oracle, j))
+    assert ex.starts_during_tick > 0
+    for call in ex.step_calls:
+        assert len(set(call)) == 1 and call[0] <= 100
