@@ -21,10 +21,12 @@
 //    (both products rounded before the difference), so the total population is conserved
 //    to rounding noise. Magnetisation and moments use the stay form (a 1e-16 bias per
 //    step is far below any tolerance).
-//  - Mixed path (float storage and float hop probabilities): P_out is summed in double,
-//    where six floats add exactly, so stay(i) = 1 - P_out is exact and the update
-//    stay * x_i + sum is finished in double before the one rounding to float; every
-//    remaining rounding is unbiased.
+//  - Mixed path (float storage and float hop probabilities): P_out is summed in double. Six
+//    floats add exactly in double while their exponents lie within about 29 binary orders
+//    (free-energy steps up to about 20 kT among the links of a site), and stay(i) =
+//    1 - P_out is then exact; beyond that span the smallest terms round, by at most 2^-53 of
+//    the sum. The update stay * x_i + sum is finished in double before the one rounding to
+//    float, so the rounding of each stored value is unbiased.
 // Inaccessible sites (section 2.1, Fig. 1) carry a huge finite free energy, so the same
 // arithmetic gives exact zero hop probabilities towards them, and they hold nothing. The
 // extended kernel variant (EXT) adds link mobility, both probabilities of the link i-j
@@ -139,6 +141,22 @@ struct RecAcc {
             u[0] += vu;
             return;
         }
+        // Regions come in large blocks, so the sites of a wave mostly share one: the wave then
+        // adds to that region's accumulators alone, behind a uniform branch. A wave that
+        // straddles regions adds to every accumulator through selects. Adding zero leaves an
+        // accumulator's bits unchanged (it starts at +0), so both forms give the same sums.
+        const int r0 = __builtin_amdgcn_readfirstlane(r);
+        if (__builtin_amdgcn_ballot_w64(r != r0) == 0) {
+#pragma unroll
+            for (int k = 0; k < MAXR; ++k) {
+                if (k == r0) {
+                    re[k] += vre;
+                    im[k] += vim;
+                    u[k] += vu;
+                }
+            }
+            return;
+        }
 #pragma unroll
         for (int k = 0; k < MAXR; ++k) {
             const bool hit = k == r;
@@ -248,13 +266,27 @@ __device__ inline double boltzmann_factor(double F, double fc)
     return exp(F - fc);
 }
 
+// 1/e for the factors of the FP64 path: the hardware reciprocal estimate refined by two
+// Newton-Raphson steps r <- r + r (1 - e r), each of which doubles its correct bits, to
+// within an ulp or two of 1/e; e = inf (an inaccessible site) gives 0. The factors lie in
+// [e^-700, e^700] (free-energy spans are capped at 1400 kT), where every step stays normal.
+// One value per cell serves both ends of each of its links, so the acceptances of a link
+// stay the same products at both ends whatever the last bits of 1/e.
+__device__ inline double factor_reciprocal(double e)
+{
+    double r = __builtin_amdgcn_rcp(e);
+    r = fma(r, fma(-e, r, 1.0), r);
+    r = fma(r, fma(-e, r, 1.0), r);
+    return __builtin_isinf(e) ? 0.0 : r;
+}
+
 // FP64 path: adds G = 1/E = e^{c - F} to a cell loaded with its factor E. An inaccessible site
 // (sentinel F) has E = inf, so G = 0: zero acceptance towards it.
 template <typename S, bool FID, int MSD, bool EXT>
 __device__ inline void weigh(Cell<S, FID, MSD, EXT> &c, double)
 {
     if (PerCellWeights<S>::on)
-        c.G = static_cast<S>(1.0 / static_cast<double>(c.F));
+        c.G = static_cast<S>(factor_reciprocal(static_cast<double>(c.F)));
 }
 
 // Byte offsets of one column (or halo column) in the 8-byte, S-sized and 1-byte arrays.
