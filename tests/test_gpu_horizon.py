@@ -48,3 +48,35 @@ def test_mixed_path_full_horizon(oracle):
     assert np.max(np.abs(msd - ref.msd())) <= 1e-4 * np.max(ref.msd())
     Do, _ = oracle.diffusion(ref.msd(), DT, 0.5e-9)
     np.testing.assert_allclose(D, Do, rtol=1e-4)
+
+
+def test_film_full_size_in_bench_configuration(oracle):
+    """The 2048 x 256 x 256 supercapacitor film, the benchmark's headline workload, at full
+    size in the launch configuration the benchmark times (mixed path, closed x, Boltzmann
+    start, automatic one-step plan), over a 4-step prefix: every record and the final
+    populations against the oracle element by element."""
+    from paper_2603_22553_amd.lattice import Lattice
+    f = synth.film()
+    steps = 4
+    print("# film: GPU", flush=True)
+    with Lattice(f.shape_xyz, bc=("closed", "periodic", "periodic"), precision="mixed",
+                 n_regions=3, max_records=steps + 1) as lat:
+        lat.set_fields(f)
+        lat.init_state("boltzmann")
+        lat.run(steps)
+        assert "steps per pass 1" in lat.describe()
+        rec = lat.records()
+        rho = lat.population().reshape(-1)
+    print("# film: oracle", flush=True)
+    o = oracle.run(f.F, f.delta, f.region, 3, steps, bc=(oracle.CLOSED, oracle.PERIODIC,
+                                                          oracle.PERIODIC), init="boltzmann")
+    for r in range(3):
+        G = rec[:, 2 * r] + 1j * rec[:, 2 * r + 1]
+        assert np.linalg.norm(G - o.fid(r)) / np.linalg.norm(o.fid(r)) <= 1e-5, r
+    U, Uo = rec[:, 6:9], o.records[:, 6:9]
+    assert np.max(np.abs(U - Uo)) <= 1e-9 * Uo.sum(axis=1).max()
+    mass = U.sum(axis=1)
+    assert np.max(np.abs(mass / mass[0] - 1.0)) <= 1e-12
+    S, So = rec[:, 9:15], o.records[:, 9:15]
+    assert np.max(np.abs(S - So)) <= 1e-5 * np.max(np.abs(So))
+    assert np.max(np.abs(rho - o.rho)) <= 1e-6 * np.max(o.rho)

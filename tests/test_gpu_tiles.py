@@ -105,6 +105,47 @@ def test_linear_tiles_other_track_sets(oracle, track):
     assert np.max(np.abs(lin["rho"].reshape(-1) - ref.rho)) <= 1e-10 * np.max(ref.rho)
 
 
+# Lattices wider than a 256-site row: many block tiles per row, a ragged last tile (as
+# narrow as one site), z chunks of 2 and 3 planes.
+WIDE = [
+    ((300, 20, 8), (1, 0, 0), "fp64"),     # 64-wide tiles: 5 per row, 32: 10, 16: 19
+    ((520, 9, 6), (0, 0, 1), "mixed"),
+    ((513, 5, 7), (0, 1, 0), "fp64"),      # a last tile one site wide
+]
+
+
+@pytest.mark.parametrize("geom", WIDE, ids=lambda g: "x".join(map(str, g[0])) + "-" +
+                         "".join("PC"[b] for b in g[1]) + "-" + g[2])
+def test_wide_lattices(oracle, geom):
+    """Every tile of a wide lattice runs exactly once: each block width and z chunk gives
+    the same state bits, the records agree to rounding and repeat bit for bit, and the
+    oracle agrees."""
+    shape, bc, precision = geom
+    f = synth.random_fields(shape, seed=sum(shape) * 3 + bc[0], n_regions=2, F_scale=1.0,
+                            delta_scale=6.0)
+    steps = 60
+    runs = {plan: run(f, bc, precision, plan, steps) for plan in ((64, 3), (32, 0), (16, 2))}
+    again = run(f, bc, precision, (64, 3), steps)
+    base = runs[(64, 3)]
+    assert np.array_equal(again["records"], base["records"])
+    for plan, r in runs.items():
+        assert r["plan"] == plan[0]
+        assert r["state"] == base["state"], plan
+        assert np.array_equal(r["rho"], base["rho"]) and np.array_equal(r["m"], base["m"])
+        assert np.allclose(r["records"], base["records"], rtol=1e-12,
+                           atol=1e-12 * np.max(np.abs(base["records"])))
+    R = f.n_regions
+    ref = oracle.run(f.F, f.delta, f.region, R, steps, bc=bc, init="boltzmann")
+    strict = precision == "fp64"
+    rec = base["records"]
+    G = rec[:, 0:2 * R:2].sum(1) + 1j * rec[:, 1:2 * R:2].sum(1)
+    assert rel_l2(G, ref.fid()) <= (1e-10 if strict else 1e-3)
+    er = np.max(np.abs(base["rho"].reshape(-1) - ref.rho)) / np.max(ref.rho)
+    assert er <= (1e-10 if strict else 1e-5)
+    S, So = rec[:, 3 * R:], ref.records[:, 3 * R:]
+    assert np.max(np.abs(S - So)) / max(np.max(np.abs(So)), 1.0) <= (1e-10 if strict else 1e-4)
+
+
 def test_linear_tile_choice_and_limits():
     """Automatic plans take linear tiles where they leave fewer lanes idle; linear tiles
     are refused beyond the widest row of the variant and for the extended variant."""
