@@ -830,6 +830,22 @@ __device__ __forceinline__ void plane_step(LDS &L, const StepArgs &a, const Tile
 #define LPC_MIN_WAVES 2
 #endif
 
+// Waves per SIMD the register allocation of a one-step sweep instance must leave room for.
+// A float linear tile's LDS window admits three workgroups per compute unit; the instances
+// with FID + moments over up to four regions and FID alone over up to eight would otherwise
+// take 170-171 VGPRs, one wave per SIMD fewer than the LDS allows. With three waves they fit
+// in 168 without spilling (four 100 x 100 x 300 systems in one batch: 36.7 -> 43.3 GSU/s).
+// Block tiles keep two: the same bound costs them 1-2 %, and four waves (128 VGPRs, with
+// spills) 8 % or more.
+template <typename S, bool FID, int MSD, bool EXT, int MAXR, int TX>
+constexpr int sweep_min_waves()
+{
+    if (sizeof(S) == 4 && TX == kTileLinear &&
+        ((MSD == 1 && MAXR > 2 && MAXR <= 4) || (MSD == 0 && FID && MAXR > 4)))
+        return 3;
+    return LPC_MIN_WAVES;
+}
+
 // Tile geometry of the sweep: TY rows of TX columns with a one-site halo, or a linear tile
 // of 256 sites with a window of one row on either side (NL cells in LDS).
 template <typename S, bool FID, int MSD, bool EXT, int TX>
@@ -1045,7 +1061,7 @@ __device__ __forceinline__ void sweep_tile(const StepArgs &a, const SweepPlan &p
 // of the step with parity 0; parity 1 swaps source and destination. Each lattice keeps its
 // own plan, so a lattice gives the same bits alone (a list of one) and in any batch.
 template <typename S, bool FID, int MSD, bool EXT, int MAXR, int TX>
-__global__ __launch_bounds__(kThreads, LPC_MIN_WAVES) void k_sweep_tile(
+__global__ __launch_bounds__(kThreads, (sweep_min_waves<S, FID, MSD, EXT, MAXR, TX>())) void k_sweep_tile(
     const SweepItem *__restrict__ items, const int64_t *__restrict__ prefix, int32_t n_items,
     int64_t total, int64_t padded, int32_t parity, int64_t slot)
 {
