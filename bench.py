@@ -38,6 +38,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Byte gap the library's arena leaves between consecutive large arrays beyond their sizes;
+# the column-stream calibration carves its arrays with the same gap, so it streams the
+# sweep's layout.
+ARENA_STAGGER = 64 * 1024 + 256
 SWEEP_SRC = os.path.join(ROOT, "paper_2603_22553_amd", "csrc", "sweep.hip")
 PROFILES = os.path.join(ROOT, "profiles")
 METRIC = "Glattice-site-updates/s (GSU/s) and fraction of HBM roofline"
@@ -737,8 +741,9 @@ def columns_rate(steps):
     from paper_2603_22553_amd import _native as N
     side, zc = 256, 128
     sites = side ** 3
-    buf = torch.rand(21 * sites, dtype=torch.float64, device="cuda")
-    arr = [buf[k * sites:(k + 1) * sites] for k in range(21)]
+    gap = sites + ARENA_STAGGER // 8
+    buf = torch.rand(21 * gap, dtype=torch.float64, device="cuda")
+    arr = [buf[k * gap:k * gap + sites] for k in range(21)]
     ins = (ctypes.c_void_p * 12)(*[t.data_ptr() for t in arr[:12]])
     outs = (ctypes.c_void_p * 9)(*[t.data_ptr() for t in arr[12:]])
     s = torch.cuda.current_stream()
@@ -764,10 +769,11 @@ def columns_mixed_rate(steps):
     from paper_2603_22553_amd import _native as N
     side, zc = 256, 128
     sites = side ** 3
-    rho = torch.rand(2 * sites, dtype=torch.float64, device="cuda")
-    flt = torch.rand(18 * sites, dtype=torch.float32, device="cuda")
+    gap_d, gap_f = sites + ARENA_STAGGER // 8, sites + ARENA_STAGGER // 4
+    rho = torch.rand(2 * gap_d, dtype=torch.float64, device="cuda")
+    flt = torch.rand(18 * gap_f, dtype=torch.float32, device="cuda")
     reg = torch.randint(0, 2, (sites,), dtype=torch.uint8, device="cuda")
-    f = [flt[k * sites:(k + 1) * sites] for k in range(18)]
+    f = [flt[k * gap_f:k * gap_f + sites] for k in range(18)]
     ins = (ctypes.c_void_p * 10)(*[t.data_ptr() for t in f[:10]])
     outs = (ctypes.c_void_p * 8)(*[t.data_ptr() for t in f[10:]])
     s = torch.cuda.current_stream()
@@ -775,7 +781,7 @@ def columns_mixed_rate(steps):
     def columns():
         for _ in range(steps):
             N.call("lpc_stream_columns_mixed", ctypes.c_void_p(rho.data_ptr()), ins,
-                   ctypes.c_void_p(reg.data_ptr()), ctypes.c_void_p(rho[sites:].data_ptr()), outs,
+                   ctypes.c_void_p(reg.data_ptr()), ctypes.c_void_p(rho[gap_d:].data_ptr()), outs,
                    side, side, side, zc, ctypes.c_void_p(s.cuda_stream))
 
     timed(s, columns)

@@ -44,6 +44,13 @@ lpc_status ok()
     } while (0)
 
 constexpr size_t kAlign = 256;
+// Arena arrays of at least kStaggerMin bytes start kStagger bytes further apart than their
+// sizes require. With a power-of-two site count every per-site array would otherwise begin
+// at the same offset modulo the L2 set and HBM channel interleaves, so the same site of all
+// of them would compete for one set and one channel. Measured on the 256^3 particle: +2 %
+// (mixed) and +4.5 % (FP64); on the 2048 x 256 x 256 film +2 %.
+constexpr size_t kStagger = 64 * 1024 + 256;
+constexpr size_t kStaggerMin = size_t(1) << 20;
 constexpr int64_t kStagingMax = int64_t(1) << 22;   // doubles per host<->device chunk
 constexpr int64_t kPartialBudget = int64_t(32) << 20; // bytes of per-step partials per chunk
 constexpr int64_t kChunkMax = 256;                    // steps finalised together
@@ -215,7 +222,7 @@ Layout plan_layout(const lpc_config &c)
     size_t o = 0;
     auto take = [&](size_t bytes) {
         const size_t at = o;
-        o = align_up(o + bytes);
+        o = align_up(o + bytes) + (bytes >= kStaggerMin ? kStagger : 0);
         return at;
     };
     const size_t ns = size_t(L.n) * L.storage;
