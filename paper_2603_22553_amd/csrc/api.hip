@@ -376,10 +376,20 @@ SoloTables solo_tables(const lpc_lattice *lat)
     return tables;
 }
 
+// A copy on the lattice's stream, waited for. A plain hipMemcpy runs on the null stream and
+// would also wait for unrelated work queued there, such as a batch stepped on the default
+// stream while this lattice is set up or read.
+hipError_t copy_sync(const lpc_lattice *lat, void *dst, const void *src, size_t bytes,
+                     hipMemcpyKind kind)
+{
+    const hipError_t e = hipMemcpyAsync(dst, src, bytes, kind, lat->stream);
+    return e == hipSuccess ? hipStreamSynchronize(lat->stream) : e;
+}
+
 lpc_status upload_solo(lpc_lattice *lat)
 {
     const SoloTables tables = solo_tables(lat);
-    LPC_HIP(hipMemcpy(lat->solo(), &tables, sizeof tables, hipMemcpyHostToDevice));
+    LPC_HIP(copy_sync(lat, lat->solo(), &tables, sizeof tables, hipMemcpyHostToDevice));
     return LPC_OK;
 }
 
@@ -424,7 +434,7 @@ lpc_status fetch_records(lpc_lattice *lat, std::vector<double> &rec)
         return s;
     const int64_t rows = lat->steps_done + 1;
     rec.resize(size_t(rows) * lat->L.K);
-    LPC_HIP(hipMemcpy(rec.data(), lat->records(), rec.size() * 8, hipMemcpyDeviceToHost));
+    LPC_HIP(copy_sync(lat, rec.data(), lat->records(), rec.size() * 8, hipMemcpyDeviceToHost));
     return LPC_OK;
 }
 
@@ -596,7 +606,7 @@ lpc_status lpc_create(const lpc_config *cfg, void *arena, size_t arena_bytes, vo
     }
     const size_t ns = size_t(L.n) * L.storage;
     const SoloTables tables = solo_tables(lat);
-    hipError_t e = hipMemcpy(lat->solo(), &tables, sizeof tables, hipMemcpyHostToDevice);
+    hipError_t e = copy_sync(lat, lat->solo(), &tables, sizeof tables, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemsetAsync(lat->at(L.off_F), 0, ns, lat->stream);
     if (e == hipSuccess && cfg->precision == LPC_PREC_FP64)   // e^{0 - 0} of the cleared field
@@ -922,7 +932,7 @@ lpc_status lpc_equilibrate(lpc_lattice *lat, int64_t max_steps, double tol, int6
                                        lat->L.n, part, kChangeParts, out, lat->stream));
         if (lpc_status s = sync(lat))
             return s;
-        LPC_HIP(hipMemcpy(change, out, 16, hipMemcpyDeviceToHost));
+        LPC_HIP(copy_sync(lat, change, out, 16, hipMemcpyDeviceToHost));
         if (!std::isfinite(change[0]) || !std::isfinite(change[1]))
             return fail(LPC_ERR_NONFINITE, "populations are not finite after %lld steps",
                         (long long)done);
@@ -995,7 +1005,7 @@ lpc_status lpc_read_population(lpc_lattice *lat, double *rho, int64_t n)
         return fail(LPC_ERR_STATE, "state not initialised");
     if (lpc_status s = sync(lat))
         return s;
-    LPC_HIP(hipMemcpy(rho, lat->st[lat->cur].rho, size_t(n) * 8, hipMemcpyDeviceToHost));
+    LPC_HIP(copy_sync(lat, rho, lat->st[lat->cur].rho, size_t(n) * 8, hipMemcpyDeviceToHost));
     return ok();
 }
 
@@ -1015,14 +1025,14 @@ lpc_status lpc_read_magnetization(lpc_lattice *lat, double *re, double *im, int6
         return s;
     const lpc::StateView &v = lat->st[lat->cur];
     if (lat->L.storage == 8) {
-        LPC_HIP(hipMemcpy(re, v.re, size_t(n) * 8, hipMemcpyDeviceToHost));
-        LPC_HIP(hipMemcpy(im, v.im, size_t(n) * 8, hipMemcpyDeviceToHost));
+        LPC_HIP(copy_sync(lat, re, v.re, size_t(n) * 8, hipMemcpyDeviceToHost));
+        LPC_HIP(copy_sync(lat, im, v.im, size_t(n) * 8, hipMemcpyDeviceToHost));
     } else {
         std::vector<float> tmp(static_cast<size_t>(n));
-        LPC_HIP(hipMemcpy(tmp.data(), v.re, size_t(n) * 4, hipMemcpyDeviceToHost));
+        LPC_HIP(copy_sync(lat, tmp.data(), v.re, size_t(n) * 4, hipMemcpyDeviceToHost));
         for (int64_t i = 0; i < n; ++i)
             re[i] = tmp[size_t(i)];
-        LPC_HIP(hipMemcpy(tmp.data(), v.im, size_t(n) * 4, hipMemcpyDeviceToHost));
+        LPC_HIP(copy_sync(lat, tmp.data(), v.im, size_t(n) * 4, hipMemcpyDeviceToHost));
         for (int64_t i = 0; i < n; ++i)
             im[i] = tmp[size_t(i)];
     }
@@ -1156,31 +1166,31 @@ lpc_status lpc_save_state(lpc_lattice *lat, void *buf, size_t cap, size_t *len)
     p += sizeof h;
     const lpc::StateView &v = lat->st[lat->cur];
     const size_t n = size_t(lat->L.n), ns = n * lat->L.storage;
-    LPC_HIP(hipMemcpy(p, v.rho, n * 8, hipMemcpyDeviceToHost));
+    LPC_HIP(copy_sync(lat, p, v.rho, n * 8, hipMemcpyDeviceToHost));
     p += n * 8;
     if (fid_of(lat->cfg)) {
-        LPC_HIP(hipMemcpy(p, v.re, ns, hipMemcpyDeviceToHost));
+        LPC_HIP(copy_sync(lat, p, v.re, ns, hipMemcpyDeviceToHost));
         p += ns;
-        LPC_HIP(hipMemcpy(p, v.im, ns, hipMemcpyDeviceToHost));
+        LPC_HIP(copy_sync(lat, p, v.im, ns, hipMemcpyDeviceToHost));
         p += ns;
     }
     if (msd_of(lat->cfg)) {
         for (int a = 0; a < 3; ++a) {
-            LPC_HIP(hipMemcpy(p, v.m1[a], ns, hipMemcpyDeviceToHost));
+            LPC_HIP(copy_sync(lat, p, v.m1[a], ns, hipMemcpyDeviceToHost));
             p += ns;
         }
         for (int a = 0; a < 3; ++a) {
-            LPC_HIP(hipMemcpy(p, v.m2[a], ns, hipMemcpyDeviceToHost));
+            LPC_HIP(copy_sync(lat, p, v.m2[a], ns, hipMemcpyDeviceToHost));
             p += ns;
         }
     }
     if (vacf_of(lat->cfg)) {
         for (int a = 0; a < 3; ++a) {
-            LPC_HIP(hipMemcpy(p, v.v[a], ns, hipMemcpyDeviceToHost));
+            LPC_HIP(copy_sync(lat, p, v.v[a], ns, hipMemcpyDeviceToHost));
             p += ns;
         }
     }
-    LPC_HIP(hipMemcpy(p, lat->records(), size_t(rows) * lat->L.K * 8, hipMemcpyDeviceToHost));
+    LPC_HIP(copy_sync(lat, p, lat->records(), size_t(rows) * lat->L.K * 8, hipMemcpyDeviceToHost));
     *len = need;
     return ok();
 }
@@ -1215,31 +1225,31 @@ lpc_status lpc_load_state(lpc_lattice *lat, const void *buf, size_t len)
     lat->cur = 0;
     const lpc::StateView &v = lat->st[0];
     const size_t n = size_t(lat->L.n), ns = n * lat->L.storage;
-    LPC_HIP(hipMemcpy(v.rho, p, n * 8, hipMemcpyHostToDevice));
+    LPC_HIP(copy_sync(lat, v.rho, p, n * 8, hipMemcpyHostToDevice));
     p += n * 8;
     if (fid_of(lat->cfg)) {
-        LPC_HIP(hipMemcpy(v.re, p, ns, hipMemcpyHostToDevice));
+        LPC_HIP(copy_sync(lat, v.re, p, ns, hipMemcpyHostToDevice));
         p += ns;
-        LPC_HIP(hipMemcpy(v.im, p, ns, hipMemcpyHostToDevice));
+        LPC_HIP(copy_sync(lat, v.im, p, ns, hipMemcpyHostToDevice));
         p += ns;
     }
     if (msd_of(lat->cfg)) {
         for (int a = 0; a < 3; ++a) {
-            LPC_HIP(hipMemcpy(v.m1[a], p, ns, hipMemcpyHostToDevice));
+            LPC_HIP(copy_sync(lat, v.m1[a], p, ns, hipMemcpyHostToDevice));
             p += ns;
         }
         for (int a = 0; a < 3; ++a) {
-            LPC_HIP(hipMemcpy(v.m2[a], p, ns, hipMemcpyHostToDevice));
+            LPC_HIP(copy_sync(lat, v.m2[a], p, ns, hipMemcpyHostToDevice));
             p += ns;
         }
     }
     if (vacf_of(lat->cfg)) {
         for (int a = 0; a < 3; ++a) {
-            LPC_HIP(hipMemcpy(v.v[a], p, ns, hipMemcpyHostToDevice));
+            LPC_HIP(copy_sync(lat, v.v[a], p, ns, hipMemcpyHostToDevice));
             p += ns;
         }
     }
-    LPC_HIP(hipMemcpy(lat->records(), p, size_t(h.rows) * lat->L.K * 8, hipMemcpyHostToDevice));
+    LPC_HIP(copy_sync(lat, lat->records(), p, size_t(h.rows) * lat->L.K * 8, hipMemcpyHostToDevice));
     lat->steps_done = h.steps_done;
     lat->initialized = true;
     return ok();
@@ -1276,7 +1286,7 @@ lpc_status device_spectrum(lpc_lattice *lat, int32_t region, int64_t L, double *
     std::vector<double> row0(size_t(lat->L.K));
     if (lpc_status s = sync(lat))
         return s;
-    LPC_HIP(hipMemcpy(row0.data(), lat->records(), row0.size() * 8, hipMemcpyDeviceToHost));
+    LPC_HIP(copy_sync(lat, row0.data(), lat->records(), row0.size() * 8, hipMemcpyDeviceToHost));
     double c = 0.0, d = 0.0;
     for (int r = 0; r < R; ++r)
         if (region < 0 || r == region) {
@@ -1316,8 +1326,8 @@ lpc_status lpc_spectrum(lpc_lattice *lat, int32_t region, int64_t n_fft, double 
         return s;
     if (lpc_status s = sync(lat))
         return s;
-    LPC_HIP(hipMemcpy(re, sorted, size_t(L) * 8, hipMemcpyDeviceToHost));
-    LPC_HIP(hipMemcpy(im, sorted + L, size_t(L) * 8, hipMemcpyDeviceToHost));
+    LPC_HIP(copy_sync(lat, re, sorted, size_t(L) * 8, hipMemcpyDeviceToHost));
+    LPC_HIP(copy_sync(lat, im, sorted + L, size_t(L) * 8, hipMemcpyDeviceToHost));
     // frequency axis of the sorted bins: f_j = (j - L/2) / (L dt), in ppm of the Larmor frequency
     const double step = 1e6 / (double(L) * lat->cfg.dt_s * lat->cfg.larmor_hz);
     for (int64_t j = 0; j < L; ++j)
@@ -1342,14 +1352,14 @@ lpc_status lpc_spectrum_peak(lpc_lattice *lat, int32_t region, double *peak_ppm)
     if (lpc_status s = sync(lat))
         return s;
     int64_t j = -1;
-    LPC_HIP(hipMemcpy(&j, where, 8, hipMemcpyDeviceToHost));
+    LPC_HIP(copy_sync(lat, &j, where, 8, hipMemcpyDeviceToHost));
     if (j < 0)
         return fail(LPC_ERR_NONFINITE, "spectrum has no finite maximum");
     const double step = 1e6 / (double(L) * lat->cfg.dt_s * lat->cfg.larmor_hz);
     double off = 0.0;
     if (j > 0 && j < L - 1) {
         double y[3];
-        LPC_HIP(hipMemcpy(y, sorted + j - 1, 24, hipMemcpyDeviceToHost));
+        LPC_HIP(copy_sync(lat, y, sorted + j - 1, 24, hipMemcpyDeviceToHost));
         // vertex of the parabola through the three highest bins
         const double den = y[0] - 2.0 * y[1] + y[2];
         off = den != 0.0 ? 0.5 * (y[0] - y[2]) / den : 0.0;
@@ -1481,7 +1491,7 @@ lpc_status lpc_region_moments(lpc_lattice *lat, double *sums, int64_t cap)
     LPC_HIP(lpc::launch_finalize(lat->partials(), kParts, 7 * R, 1, dev, lat->stream));
     if (lpc_status s = sync(lat))
         return s;
-    LPC_HIP(hipMemcpy(sums, dev, size_t(7 * R) * 8, hipMemcpyDeviceToHost));
+    LPC_HIP(copy_sync(lat, sums, dev, size_t(7 * R) * 8, hipMemcpyDeviceToHost));
     return ok();
 }
 
@@ -1505,7 +1515,7 @@ lpc_status lpc_uptake_profile(lpc_lattice *lat, int32_t axis, double *profile, i
     LPC_HIP(lpc::launch_profile(lat->st[lat->cur].rho, g, axis, dev, lat->stream));
     if (lpc_status s = sync(lat))
         return s;
-    LPC_HIP(hipMemcpy(profile, dev, size_t(n) * 8, hipMemcpyDeviceToHost));
+    LPC_HIP(copy_sync(lat, profile, dev, size_t(n) * 8, hipMemcpyDeviceToHost));
     return ok();
 }
 
