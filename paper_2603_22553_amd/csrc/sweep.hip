@@ -743,11 +743,28 @@ struct TileThread {
     uint32_t ghosts;         // bits 0..3: the x-1, x+1, y-1, y+1 neighbour is a reservoir ghost
 };
 
-// One z-plane of the tile: stage it in LDS buffer `L` (own site + halo site), prefetch
-// plane z+2 (own column) into `nx2` and the halo of plane z+1 into `halo`, wait for the
-// whole tile, then update every site of the plane from LDS (x, y) and registers (z).
+// Whether a sweep instance fetches its halo two planes ahead into a third LDS buffer (float
+// block tiles of the plain variant, without autocorrelation tags) rather than one plane
+// ahead into the other of two. A halo row is a row its neighbour tile loads for itself two
+// planes ahead; fetched at the same time, the second load finds the row in L2. One plane
+// later, on a lattice with wide rows, it mostly does not: the neighbour row then belongs to
+// a tile launched a whole tile row earlier or later, which is at another plane. The third
+// buffer leaves these tiles as many resident workgroups per CU as their registers allow
+// (three with FID and moments, six with FID alone or populations alone); FP64, tagged
+// cells, moments without FID and linear tiles would lose a workgroup to it.
+template <typename S, bool FID, int MSD, bool EXT, int TX>
+constexpr bool early_halo()
+{
+    return sizeof(S) == 4 && (FID ? MSD < 2 : MSD == 0) && !EXT && TX != kTileLinear;
+}
+
+// One z-plane of the tile: stage it in LDS buffer `L` (own site, and the halo site unless
+// the halo comes early), prefetch plane z+2 (own column) into `nx2` and the halo of plane
+// z+1 into `halo` (early halo: put the halo of plane z+1, fetched a plane ago, into `Ln`, the
+// buffer of plane z+1, and fetch that of plane z+2), wait for the whole tile, then update
+// every site of the plane from LDS (x, y) and registers (z).
 template <typename S, bool FID, int MSD, bool EXT, int MAXR, int TX, typename LDS>
-__device__ __forceinline__ void plane_step(LDS &L, const StepArgs &a, const TileThread &th,
+__device__ __forceinline__ void plane_step(LDS &L, LDS &Ln, const StepArgs &a, const TileThread &th,
                                            const View<S> &src, const View<S> &dst, const S *F,
                                            const S *MU, const S *TH, int64_t plane, int z,
                                            int z1, const Cell<S, FID, MSD, EXT> &prv,
@@ -756,11 +773,17 @@ __device__ __forceinline__ void plane_step(LDS &L, const StepArgs &a, const Tile
                                            Cell<S, FID, MSD, EXT> &nx2,
                                            Cell<S, FID, MSD, EXT> &halo, RecAcc<MAXR> &acc)
 {
+    constexpr bool EARLY = early_halo<S, FID, MSD, EXT, TX>();
     const Geometry &g = a.g;
     const bool zper = g.bc[2] == 0, zres = EXT && g.bc[2] == kBcReservoir;
     if (th.act)
         L.put(th.li, cur);
-    if (th.hslot >= 0) {
+    if (EARLY) {
+        if (th.hslot >= 0 && z + 1 < z1) {
+            weigh(halo, a.fc);
+            Ln.put(th.hslot, halo);
+        }
+    } else if (th.hslot >= 0) {
         if (!EXT || th.hghost < 0)      // a loaded halo cell; a ghost one is weighed already
             weigh(halo, a.fc);
         L.put(th.hslot, halo);
@@ -777,9 +800,11 @@ __device__ __forceinline__ void plane_step(LDS &L, const StepArgs &a, const Tile
         const int zn = z + 2 < g.nz ? z + 2 : (zper ? 0 : -1);
         if (th.act && zn >= 0)
             load_cell(nx2, src, F, MU, plane * zn, own);
-        if (th.hslot >= 0 && (!EXT || th.hghost < 0))
+        if (!EARLY && th.hslot >= 0 && (!EXT || th.hghost < 0))
             load_cell(halo, src, F, MU, plane * (z + 1), hal);
     }
+    if (EARLY && th.hslot >= 0 && z + 2 < z1)
+        load_cell(halo, src, F, MU, plane * (z + 2), hal);
     __syncthreads();
     if (!th.act)
         return;
@@ -998,8 +1023,9 @@ __device__ __forceinline__ void sweep_tile(const StepArgs &a, const SweepPlan &p
 {
     using Shape = TileShape<S, FID, MSD, EXT, TX>;
     constexpr int NL = Shape::NL;
+    constexpr bool EARLY = early_halo<S, FID, MSD, EXT, TX>();
     using C = Cell<S, FID, MSD, EXT>;
-    __shared__ TileLds<S, FID, MSD, EXT, NL> L0, L1;
+    __shared__ TileLds<S, FID, MSD, EXT, NL> Lb[EARLY ? 3 : 2];
     __shared__ double red[(kThreads / kWave) * record_slots(MAXR, MSD)];
     const Geometry &g = a.g;
     int bx, by, bz;
@@ -1034,28 +1060,44 @@ __device__ __forceinline__ void sweep_tile(const StepArgs &a, const SweepPlan &p
         weigh(w1, a.fc);
     }
     if (th.hslot >= 0) {
-        if (EXT && th.hghost >= 0)
+        if (EXT && th.hghost >= 0) {
             ghost_cell(halo, a.ghost, th.hghost, a.fc);
-        else
+        } else {
             load_cell(halo, src, F, MU, plane * z0, th.halo);
+            if (EARLY) {
+                // the first plane's halo goes straight into its buffer; the register then
+                // carries the next plane's, which the first step puts into the next buffer
+                weigh(halo, a.fc);
+                Lb[0].put(th.hslot, halo);
+                if (z0 + 1 < z1)
+                    load_cell(halo, src, F, MU, plane * (z0 + 1), th.halo);
+            }
+        }
     }
     // roles (prv, cur, nxt, in-flight) rotate through w0..w3 with period 4; LDS buffers
-    // alternate with period 2
+    // alternate with period 2, or rotate with period 3 (early halo: plane z in buffer
+    // (z - z0) mod 3)
+    int b = 0;
+    auto nb = [](int i) { return EARLY ? (i == 2 ? 0 : i + 1) : 1 - i; };
     for (int z = z0; z < z1; z += 4) {
-        plane_step<S, FID, MSD, EXT, MAXR, TX>(L0, a, th, src, dst, F, MU, TH, plane, z, z1, w0,
-                                                    w1, w2, w3, halo, acc);
+        plane_step<S, FID, MSD, EXT, MAXR, TX>(Lb[b], Lb[nb(b)], a, th, src, dst, F, MU, TH,
+                                               plane, z, z1, w0, w1, w2, w3, halo, acc);
+        b = nb(b);
         if (z + 1 >= z1)
             break;
-        plane_step<S, FID, MSD, EXT, MAXR, TX>(L1, a, th, src, dst, F, MU, TH, plane, z + 1, z1, w1,
-                                                    w2, w3, w0, halo, acc);
+        plane_step<S, FID, MSD, EXT, MAXR, TX>(Lb[b], Lb[nb(b)], a, th, src, dst, F, MU, TH,
+                                               plane, z + 1, z1, w1, w2, w3, w0, halo, acc);
+        b = nb(b);
         if (z + 2 >= z1)
             break;
-        plane_step<S, FID, MSD, EXT, MAXR, TX>(L0, a, th, src, dst, F, MU, TH, plane, z + 2, z1, w2,
-                                                    w3, w0, w1, halo, acc);
+        plane_step<S, FID, MSD, EXT, MAXR, TX>(Lb[b], Lb[nb(b)], a, th, src, dst, F, MU, TH,
+                                               plane, z + 2, z1, w2, w3, w0, w1, halo, acc);
+        b = nb(b);
         if (z + 3 >= z1)
             break;
-        plane_step<S, FID, MSD, EXT, MAXR, TX>(L1, a, th, src, dst, F, MU, TH, plane, z + 3, z1, w3,
-                                                    w0, w1, w2, halo, acc);
+        plane_step<S, FID, MSD, EXT, MAXR, TX>(Lb[b], Lb[nb(b)], a, th, src, dst, F, MU, TH,
+                                               plane, z + 3, z1, w3, w0, w1, w2, halo, acc);
+        b = nb(b);
     }
     __syncthreads();
     block_reduce<MAXR, kThreads / kWave, MSD == 2>(acc, a.R, a.K, a.partials, p.nblocks, blk, red);
