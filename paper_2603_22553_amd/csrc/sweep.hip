@@ -750,12 +750,14 @@ struct TileThread {
 // later, on a lattice with wide rows, it mostly does not: the neighbour row then belongs to
 // a tile launched a whole tile row earlier or later, which is at another plane. The third
 // buffer leaves these tiles as many resident workgroups per CU as their registers allow
-// (three with FID and moments, six with FID alone or populations alone); FP64, tagged
-// cells, moments without FID and linear tiles would lose a workgroup to it.
+// (three with FID and moments, six with FID alone); FP64, tagged cells, moments without
+// FID and linear tiles would lose a workgroup to it. The population-only sweep, whose short
+// z-chunks pay the longer start more often, ran 3 % slower with it and keeps the one-plane
+// halo. Measured on the 256^3 particle with FID alone: 102.0 -> 110.5 GSU/s.
 template <typename S, bool FID, int MSD, bool EXT, int TX>
 constexpr bool early_halo()
 {
-    return sizeof(S) == 4 && (FID ? MSD < 2 : MSD == 0) && !EXT && TX != kTileLinear;
+    return sizeof(S) == 4 && FID && MSD < 2 && !EXT && TX != kTileLinear;
 }
 
 // One z-plane of the tile: stage it in LDS buffer `L` (own site, and the halo site unless
