@@ -35,6 +35,9 @@
  *  - Streams: work is queued on the stream given at creation (a hipStream_t passed as
  *    void*, NULL = the null stream). lpc_run returns once the work is queued; device
  *    errors surface at the next lpc_synchronize or read. Reads synchronize the stream.
+ *    Every copy between host and device also runs on that stream, so a call that waits
+ *    (a set, a read, a checkpoint) waits for the lattice's own work only, not for work
+ *    queued on other streams.
  *  - A handle is not thread-safe: one thread at a time may use it.
  */
 #ifndef LPC_H
