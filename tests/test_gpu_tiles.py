@@ -226,3 +226,26 @@ def test_batch_mixing_linear_and_block_tiles_is_bitwise_solo():
     finally:
         for lat in lats:
             lat.close()
+
+
+@pytest.mark.parametrize("track", [("fid", "msd"), ("fid",)], ids=["fid+msd", "fid"])
+def test_early_halo_chunks_and_widths(oracle, track):
+    """Float block tiles fetch their halo two planes ahead into a third LDS buffer. Every
+    z-chunk length (1, 2, 3, 5 planes and the automatic one), every block width and the
+    linear tiles (one-plane halo) give the same state bits, and the oracle agrees; the
+    lattice has ragged tiles in x and y and closed faces in y and z."""
+    shape, bc = (70, 11, 13), (0, 1, 1)
+    f = synth.random_fields(shape, seed=7013, n_regions=2, F_scale=1.0, delta_scale=6.0)
+    steps = 40
+    plans = [(64, 1), (64, 2), (32, 3), (16, 5), (64, 0), (1, 0)]
+    runs = [run(f, bc, "mixed", plan, steps, track=track) for plan in plans]
+    for plan, r in zip(plans, runs):
+        assert r["plan"] == plan[0]
+        assert r["state"] == runs[0]["state"], plan
+        assert np.array_equal(r["rho"], runs[0]["rho"]) and np.array_equal(r["m"], runs[0]["m"])
+    ref = oracle.run(f.F, f.delta, f.region, 2, steps, bc=bc, init="boltzmann",
+                     moments="msd" in track)
+    rec = runs[0]["records"]
+    G = rec[:, 0:4:2].sum(1) + 1j * rec[:, 1:4:2].sum(1)
+    assert rel_l2(G, ref.fid()) <= 1e-3
+    assert np.max(np.abs(runs[0]["rho"].reshape(-1) - ref.rho)) <= 1e-5 * np.max(ref.rho)
