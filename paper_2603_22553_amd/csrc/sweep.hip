@@ -760,10 +760,22 @@ constexpr bool early_halo()
     return sizeof(S) == 4 && FID && MSD < 2 && !EXT && TX != kTileLinear;
 }
 
+// The FP64 sweep with FID and moments fetches its halo two planes ahead too, into a second
+// halo register set that alternates with the first from plane to plane: its LDS already
+// allows only two workgroups per CU, which its registers (up to 256 with the extra set, to
+// four regions) allow as well. Its halo threads read fewer lines from HBM; FID alone and
+// more regions would lose a workgroup or spill.
+template <typename S, bool FID, int MSD, bool EXT, int MAXR, int TX>
+constexpr bool early_halo_regs()
+{
+    return sizeof(S) == 8 && FID && MSD == 1 && !EXT && MAXR <= 4 && TX != kTileLinear;
+}
+
 // One z-plane of the tile: stage it in LDS buffer `L` (own site, and the halo site unless
 // the halo comes early), prefetch plane z+2 (own column) into `nx2` and the halo of plane
 // z+1 into `halo` (early halo: put the halo of plane z+1, fetched a plane ago, into `Ln`, the
-// buffer of plane z+1, and fetch that of plane z+2), wait for the whole tile, then update
+// buffer of plane z+1, and fetch that of plane z+2; two halo registers: `halo` holds the
+// halo of plane z and receives that of plane z+2), wait for the whole tile, then update
 // every site of the plane from LDS (x, y) and registers (z).
 template <typename S, bool FID, int MSD, bool EXT, int MAXR, int TX, typename LDS>
 __device__ __forceinline__ void plane_step(LDS &L, LDS &Ln, const StepArgs &a, const TileThread &th,
@@ -776,6 +788,7 @@ __device__ __forceinline__ void plane_step(LDS &L, LDS &Ln, const StepArgs &a, c
                                            Cell<S, FID, MSD, EXT> &halo, RecAcc<MAXR> &acc)
 {
     constexpr bool EARLY = early_halo<S, FID, MSD, EXT, TX>();
+    constexpr bool REG2 = early_halo_regs<S, FID, MSD, EXT, MAXR, TX>();
     const Geometry &g = a.g;
     const bool zper = g.bc[2] == 0, zres = EXT && g.bc[2] == kBcReservoir;
     if (th.act)
@@ -802,10 +815,10 @@ __device__ __forceinline__ void plane_step(LDS &L, LDS &Ln, const StepArgs &a, c
         const int zn = z + 2 < g.nz ? z + 2 : (zper ? 0 : -1);
         if (th.act && zn >= 0)
             load_cell(nx2, src, F, MU, plane * zn, own);
-        if (!EARLY && th.hslot >= 0 && (!EXT || th.hghost < 0))
+        if (!EARLY && !REG2 && th.hslot >= 0 && (!EXT || th.hghost < 0))
             load_cell(halo, src, F, MU, plane * (z + 1), hal);
     }
-    if (EARLY && th.hslot >= 0 && z + 2 < z1)
+    if ((EARLY || REG2) && th.hslot >= 0 && z + 2 < z1)
         load_cell(halo, src, F, MU, plane * (z + 2), hal);
     __syncthreads();
     if (!th.act)
@@ -1026,6 +1039,7 @@ __device__ __forceinline__ void sweep_tile(const StepArgs &a, const SweepPlan &p
     using Shape = TileShape<S, FID, MSD, EXT, TX>;
     constexpr int NL = Shape::NL;
     constexpr bool EARLY = early_halo<S, FID, MSD, EXT, TX>();
+    constexpr bool REG2 = early_halo_regs<S, FID, MSD, EXT, MAXR, TX>();
     using C = Cell<S, FID, MSD, EXT>;
     __shared__ TileLds<S, FID, MSD, EXT, NL> Lb[EARLY ? 3 : 2];
     __shared__ double red[(kThreads / kWave) * record_slots(MAXR, MSD)];
@@ -1046,7 +1060,9 @@ __device__ __forceinline__ void sweep_tile(const StepArgs &a, const SweepPlan &p
     const View<S> dst = typed<S>(a.dst);
     const int64_t plane = static_cast<int64_t>(g.nx) * g.ny;
     const int z0 = bz * p.zc, z1 = min(g.nz, z0 + p.zc);
-    C w0, w1, w2, w3, halo;
+    C w0, w1, w2, w3, halo, halo2;
+    // the halo register of odd planes (the same as that of even ones without REG2)
+    C &hodd = REG2 ? halo2 : halo;
     RecAcc<MAXR> acc;
     acc.zero();
     if (th.act) {
@@ -1066,6 +1082,8 @@ __device__ __forceinline__ void sweep_tile(const StepArgs &a, const SweepPlan &p
             ghost_cell(halo, a.ghost, th.hghost, a.fc);
         } else {
             load_cell(halo, src, F, MU, plane * z0, th.halo);
+            if (REG2 && z0 + 1 < z1)
+                load_cell(halo2, src, F, MU, plane * (z0 + 1), th.halo);
             if (EARLY) {
                 // the first plane's halo goes straight into its buffer; the register then
                 // carries the next plane's, which the first step puts into the next buffer
@@ -1088,7 +1106,7 @@ __device__ __forceinline__ void sweep_tile(const StepArgs &a, const SweepPlan &p
         if (z + 1 >= z1)
             break;
         plane_step<S, FID, MSD, EXT, MAXR, TX>(Lb[b], Lb[nb(b)], a, th, src, dst, F, MU, TH,
-                                               plane, z + 1, z1, w1, w2, w3, w0, halo, acc);
+                                               plane, z + 1, z1, w1, w2, w3, w0, hodd, acc);
         b = nb(b);
         if (z + 2 >= z1)
             break;
@@ -1098,7 +1116,7 @@ __device__ __forceinline__ void sweep_tile(const StepArgs &a, const SweepPlan &p
         if (z + 3 >= z1)
             break;
         plane_step<S, FID, MSD, EXT, MAXR, TX>(Lb[b], Lb[nb(b)], a, th, src, dst, F, MU, TH,
-                                               plane, z + 3, z1, w3, w0, w1, w2, halo, acc);
+                                               plane, z + 3, z1, w3, w0, w1, w2, hodd, acc);
         b = nb(b);
     }
     __syncthreads();
